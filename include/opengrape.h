@@ -1,0 +1,186 @@
+/*
+ * opengrape.h -- C ABI of the exponential-free open-GRAPE library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for a batch of B independent control arrays, the
+ * performance index and its gradient of open GRAPE without matrix
+ * exponentials (Boutin et al., "Resonator reset in circuit QED by optimal
+ * control for large open quantum systems", Sec. III):
+ *
+ *   H_j   = H0 + sum_k u[j,k] H_k                               Sec. II.A, Eq. (1)
+ *   drho/dt = -i[H_j, rho] + sum_m gamma_m D[c_m] rho,
+ *   D[c] rho = c rho c^dag - {c^dag c, rho}/2                    Sec. II.B, Eqs. (3)-(4)
+ *   rho_{j+1} = RK4 integration of slice j (n_sub steps of dt/n_sub)
+ *                                                                Sec. III, Eq. (14)
+ *   Phi   = Tr(sigma rho_{N_t})                                  Sec. II.B, Eq. (8)
+ *   lambda_{N_t} = sigma, lambda_j = RK4 integration of L_j^dag  Sec. II.B, Eq. (11);
+ *                                                                Sec. III, Eq. (15)
+ *   dPhi/du[j,k] = -i dt Tr(lambda_{j+1} [H_k, rho_{j+1}])       Sec. II.B, Eq. (13)
+ *                  (OG_GRAD_GRAPE1), or the exact derivative of the
+ *                  RK4-discretised Phi (OG_GRAD_EXACT, the higher-order
+ *                  gradient mentioned after Eq. (12)).
+ *
+ * No d^2 x d^2 superoperator and no matrix exponential is ever formed.
+ *
+ * Conventions shared by every entry point
+ *  - Complex arrays are interleaved (re, im) float64 pairs, row-major, i.e.
+ *    the memory layout of numpy / torch complex128.  Control, cost and
+ *    gradient arrays are float64.  Internally the library computes in the
+ *    precision chosen at og_create (og_prec).
+ *  - "host" pointers are read during the call only.  "device" pointers are
+ *    HIP device memory owned by the caller; the library never frees them.
+ *  - Every call that takes a stream enqueues its GPU work on that
+ *    hipStream_t (NULL = the default stream) and returns without waiting,
+ *    except where stated.  Argument and launch errors are reported by the
+ *    return code; og_last_error() gives a text for the calling thread.
+ *  - Call order per evaluation: og_forward -> og_cost -> og_adjoint ->
+ *    og_gradient.  og_cost and og_adjoint may be skipped/repeated only as
+ *    stated; a call out of order returns OG_ERR_ORDER.
+ *  - One context must not be used from two host threads at once.  Contexts
+ *    are independent of each other.
+ */
+#ifndef OPENGRAPE_H
+#define OPENGRAPE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct og_ctx og_ctx;
+
+typedef enum {
+    OG_OK = 0,
+    OG_ERR_ARG = -1,           /* NULL pointer, bad size or option            */
+    OG_ERR_SHAPE = -2,         /* size limits exceeded / operator structure   */
+    OG_ERR_NOT_HERMITIAN = -3, /* H0, H_k not Hermitian (validate = 1)         */
+    OG_ERR_UNSTABLE_DT = -4,   /* dt / n_sub outside the RK4 stability bound  */
+    OG_ERR_WORKSPACE = -5,     /* workspace NULL or smaller than required     */
+    OG_ERR_ORDER = -6,         /* call out of order                          */
+    OG_ERR_NONFINITE = -7,     /* a propagated state became non-finite        */
+    OG_ERR_DEVICE = -8         /* HIP runtime error (allocation, launch)      */
+} og_status;
+
+typedef enum {
+    OG_F64 = 0,                /* float64 states and arithmetic                */
+    OG_F32 = 1                 /* float32 arithmetic; states carried as a
+                                  compensated (hi, lo) float32 pair; cost,
+                                  trace and gradient sums in float64          */
+} og_prec;
+
+typedef enum {
+    OG_GRAD_GRAPE1 = 0,        /* first-order gradient, Eq. (13)              */
+    OG_GRAD_EXACT = 1          /* exact derivative of the RK4-discretised Phi */
+} og_gmode;
+
+typedef enum {
+    OG_PATH_AUTO = 0,          /* banded if every operator has few diagonals  */
+    OG_PATH_DENSE = 1,         /* dense complex GEMMs on the matrix cores     */
+    OG_PATH_BANDED = 2         /* diagonal-storage stencil (HBM-bound)        */
+} og_path;
+
+typedef struct {
+    int prec;         /* og_prec                                                */
+    int gmode;        /* og_gmode                                               */
+    int path;         /* og_path                                                */
+    int n_sub;        /* RK4 steps per slice, >= 1 (h = dt / n_sub)             */
+    int ckpt_stride;  /* slices between stored forward states; 0 = ceil(sqrt(N_t)) */
+    int validate;     /* 1: check Hermiticity at create, RK4 stability and
+                         non-finite states per evaluation (one stream sync in
+                         og_forward and one in og_gradient)                    */
+} og_options;
+
+/* Fill *opt with the defaults: OG_F64, OG_GRAD_GRAPE1, OG_PATH_AUTO,
+ * n_sub = 1, ckpt_stride = 0, validate = 1. */
+void og_default_options(og_options *opt);
+
+/*
+ * Create a context for one operator set (Eq. (1), Eq. (4)).
+ *   d              Hilbert-space dimension, 1 <= d <= 4096.
+ *   K              number of control Hamiltonians, 0 <= K <= 16.
+ *   J              number of collapse operators, 0 <= J <= 16.
+ *   H0             host, complex128 d x d, Hermitian.
+ *   Hk             host, complex128 K x d x d, each Hermitian (NULL if K = 0).
+ *   c_ops          host, complex128 J x d x d (NULL if J = 0).
+ *   gamma          host, float64 J rates, each >= 0 (NULL if J = 0).
+ *   opt            host, options (NULL = defaults).
+ * The context owns device copies of the operators in the working precision
+ * (dense matrices or diagonal storage, per og_path).  Allocates device
+ * memory; synchronous.  Returns OG_ERR_SHAPE if OG_PATH_BANDED is forced
+ * and an operator has too many diagonals (more than 16 per operator set).
+ */
+og_status og_create(og_ctx **out, int d, int K, int J,
+                    const void *H0, const void *Hk, const void *c_ops,
+                    const double *gamma, const og_options *opt);
+
+/* Free the context and its device memory (synchronizes the device). */
+og_status og_destroy(og_ctx *ctx);
+
+/* The path the context runs (OG_PATH_DENSE or OG_PATH_BANDED). */
+int og_path_used(const og_ctx *ctx);
+
+/*
+ * Device workspace (bytes) that og_forward needs for a batch of B problems
+ * of N_t slices: working stage buffers, the stored forward states every
+ * ckpt_stride slices, one segment of recomputed states for the backward
+ * sweep, and the float64 gradient.  Memory grows as O(sqrt(N_t) d^2) per
+ * problem, not O(N_t d^2).  Returns 0 for invalid arguments.
+ */
+size_t og_workspace_bytes(const og_ctx *ctx, int B, int n_t);
+
+/*
+ * Forward sweep (Eqs. (10), (14)).
+ *   B, n_t    batch size (>= 1) and number of slices (>= 1).
+ *   dt        slice length (> 0).
+ *   u         device, float64 B x n_t x K, row-major (u[b][j][k]).
+ *   rho0      device, complex128 B x d x d initial states (Hermitian).
+ *   rhoT      device, complex128 B x d x d output rho_{N_t}, or NULL.
+ *   ws        device workspace of ws_bytes >= og_workspace_bytes(ctx, B, n_t),
+ *             256-byte aligned; it must stay allocated and untouched until
+ *             og_gradient returns.  u must stay unchanged until then too.
+ * With validate = 1, reads max|u| back to the host (one stream sync) and
+ * returns OG_ERR_UNSTABLE_DT if the RK4 step is outside the stability
+ * bound of the Gershgorin estimate of the Hamiltonian's spectral span.
+ */
+og_status og_forward(og_ctx *ctx, int B, int n_t, double dt,
+                     const double *u, const void *rho0, void *rhoT,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Performance index (Eq. (8)): phi[b] = Re Tr(sigma rho_{N_t}[b]), summed
+ * in float64 in a fixed order.
+ *   sigma     device, complex128 d x d, Hermitian, shared by the batch.
+ *   phi       device, float64 B.
+ * Requires a preceding og_forward.
+ */
+og_status og_cost(og_ctx *ctx, const void *sigma, double *phi, void *stream);
+
+/*
+ * Backward sweep (Eqs. (11), (13), (15)): lambda starts at sigma and is
+ * integrated with L_j^dag slice by slice; forward states are recomputed one
+ * segment at a time from the stored ones; the per-slice gradient
+ * (GRAPE1 or EXACT, og_gmode) is written into the workspace.
+ *   sigma     device, complex128 d x d, Hermitian (the same as for og_cost).
+ * Requires a preceding og_forward.
+ */
+og_status og_adjoint(og_ctx *ctx, const void *sigma, void *stream);
+
+/*
+ * Copy the gradient dPhi/du to grad (device, float64 B x n_t x K) and, with
+ * validate = 1, synchronize the stream and report OG_ERR_NONFINITE if a
+ * state became non-finite during forward or adjoint.  Requires og_adjoint.
+ */
+og_status og_gradient(og_ctx *ctx, double *grad, void *stream);
+
+/* Static text for a status code. */
+const char *og_status_string(og_status s);
+
+/* Detail of the last failing call on this host thread ("" if none). */
+const char *og_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPENGRAPE_H */

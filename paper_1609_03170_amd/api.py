@@ -1,0 +1,266 @@
+"""Python binding of libopengrape.so (ctypes; argument marshalling only).
+
+Every step of the propagation, cost and gradient runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  There is no CPU
+fallback: creating a Problem without the built library, or without a GPU,
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libopengrape.so")
+
+PREC = {"f64": 0, "f32": 1}
+GMODE = {"grape1": 0, "exact": 1}
+PATH = {"auto": 0, "dense": 1, "banded": 2}
+PATH_NAMES = {1: "dense", 2: "banded"}
+
+STATUS = {
+    0: "OG_OK",
+    -1: "OG_ERR_ARG",
+    -2: "OG_ERR_SHAPE",
+    -3: "OG_ERR_NOT_HERMITIAN",
+    -4: "OG_ERR_UNSTABLE_DT",
+    -5: "OG_ERR_WORKSPACE",
+    -6: "OG_ERR_ORDER",
+    -7: "OG_ERR_NONFINITE",
+    -8: "OG_ERR_DEVICE",
+}
+
+# Every symbol declared in include/opengrape.h.
+EXPORTS = (
+    "og_default_options", "og_create", "og_destroy", "og_path_used", "og_workspace_bytes",
+    "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_status_string", "og_last_error",
+)
+
+
+class OgOptions(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("gmode", ctypes.c_int), ("path", ctypes.c_int),
+                ("n_sub", ctypes.c_int), ("ckpt_stride", ctypes.c_int), ("validate", ctypes.c_int)]
+
+
+class OgError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {detail}")
+
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libopengrape.so and declare the C signatures (no GPU needed)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.og_default_options.argtypes = [ctypes.POINTER(OgOptions)]
+    lib.og_default_options.restype = None
+    lib.og_create.argtypes = [ctypes.POINTER(vp), i, i, i, vp, vp, vp, vp, ctypes.POINTER(OgOptions)]
+    lib.og_create.restype = i
+    lib.og_destroy.argtypes = [vp]
+    lib.og_destroy.restype = i
+    lib.og_path_used.argtypes = [vp]
+    lib.og_path_used.restype = i
+    lib.og_workspace_bytes.argtypes = [vp, i, i]
+    lib.og_workspace_bytes.restype = sz
+    lib.og_forward.argtypes = [vp, i, i, d, vp, vp, vp, vp, sz, vp]
+    lib.og_forward.restype = i
+    lib.og_cost.argtypes = [vp, vp, vp, vp]
+    lib.og_cost.restype = i
+    lib.og_adjoint.argtypes = [vp, vp, vp]
+    lib.og_adjoint.restype = i
+    lib.og_gradient.argtypes = [vp, vp, vp]
+    lib.og_gradient.restype = i
+    lib.og_status_string.argtypes = [i]
+    lib.og_status_string.restype = ctypes.c_char_p
+    lib.og_last_error.argtypes = []
+    lib.og_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        detail = _LIB.og_last_error().decode() if _LIB is not None else ""
+        raise OgError(status, detail)
+
+
+def _host_c128(x, shape):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Problem:
+    """One operator set (H0, H_k, c_m, gamma_m) on one GPU.
+
+    Methods mirror the C ABI: forward -> cost -> adjoint -> gradient.  All
+    tensors are on the Problem's device; controls are float64 [B, N_t, K],
+    states complex128 [B, d, d]."""
+
+    def __init__(self, H0, Hk, c_ops, gammas, *, prec="f64", gmode="grape1", path="auto", n_sub=1,
+                 ckpt_stride=0, validate=True, device=None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("opengrape needs a ROCm GPU; no device is visible")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        H0 = np.asarray(H0)
+        d = H0.shape[0]
+        Hk = np.asarray(Hk, dtype=np.complex128).reshape(-1, d, d) if len(Hk) else np.zeros((0, d, d), np.complex128)
+        c_ops = (np.asarray(c_ops, dtype=np.complex128).reshape(-1, d, d) if len(c_ops)
+                 else np.zeros((0, d, d), np.complex128))
+        self.d, self.K, self.J = d, Hk.shape[0], c_ops.shape[0]
+        self._h0 = _host_c128(H0, (d, d))
+        self._hk = np.ascontiguousarray(Hk)
+        self._c = np.ascontiguousarray(c_ops)
+        self._g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).reshape(-1))
+        if self._g.shape[0] != self.J:
+            raise ValueError("one rate per collapse operator")
+        opt = OgOptions()
+        lib.og_default_options(ctypes.byref(opt))
+        opt.prec, opt.gmode, opt.path = PREC[prec], GMODE[gmode], PATH[path]
+        opt.n_sub, opt.ckpt_stride, opt.validate = int(n_sub), int(ckpt_stride), int(bool(validate))
+        self.prec, self.gmode, self.n_sub = prec, gmode, int(n_sub)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.og_create(ctypes.byref(ctx), d, self.K, self.J, self._h0.ctypes.data,
+                                 self._hk.ctypes.data if self.K else None,
+                                 self._c.ctypes.data if self.J else None,
+                                 self._g.ctypes.data if self.J else None, ctypes.byref(opt)))
+        self._ctx = ctx
+        self._lib = lib
+        self._keep = {}
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w.H0, w.Hk, w.c_ops, w.gammas, **kw)
+
+    @property
+    def path(self) -> str:
+        return PATH_NAMES[self._lib.og_path_used(self._ctx)]
+
+    def workspace_bytes(self, B: int, n_t: int) -> int:
+        return int(self._lib.og_workspace_bytes(self._ctx, int(B), int(n_t)))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.og_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C ABI calls -------------------------------------------------------
+    def _as_u(self, u):
+        if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == torch.float64):
+            raise TypeError("u must be a float64 CUDA tensor")
+        if u.dim() == 2:
+            u = u.unsqueeze(0)
+        if u.dim() != 3 or u.shape[2] != self.K:
+            raise ValueError(f"u must be [B, N_t, {self.K}]")
+        return u.contiguous()
+
+    def _as_states(self, r, B):
+        if not (isinstance(r, torch.Tensor) and r.is_cuda and r.dtype == torch.complex128):
+            raise TypeError("states must be complex128 CUDA tensors")
+        if r.dim() == 2:
+            r = r.unsqueeze(0)
+        if r.shape[1:] != (self.d, self.d):
+            raise ValueError(f"states must be [B, {self.d}, {self.d}]")
+        if r.shape[0] == 1 and B > 1:
+            r = r.expand(B, self.d, self.d)
+        return r.contiguous()
+
+    def forward(self, u, rho0, dt, want_rho_T=False, workspace=None):
+        u = self._as_u(u)
+        B, n_t = u.shape[0], u.shape[1]
+        rho0 = self._as_states(rho0, B)
+        need = self.workspace_bytes(B, n_t)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        rhoT = torch.empty((B, self.d, self.d), dtype=torch.complex128, device=self.device) if want_rho_T else None
+        self._keep = dict(u=u, rho0=rho0, ws=workspace, B=B, n_t=n_t)
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_forward(self._ctx, B, n_t, float(dt), u.data_ptr(), rho0.data_ptr(),
+                                        rhoT.data_ptr() if rhoT is not None else None,
+                                        workspace.data_ptr(), need, _stream_ptr(self.device)))
+        return rhoT
+
+    def cost(self, sigma):
+        sigma = self._as_states(sigma, 1)[0].contiguous()
+        phi = torch.empty(self._keep.get("B", 1), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_cost(self._ctx, sigma.data_ptr(), phi.data_ptr(), _stream_ptr(self.device)))
+        self._keep["sigma"] = sigma
+        return phi
+
+    def adjoint(self, sigma):
+        sigma = self._as_states(sigma, 1)[0].contiguous()
+        self._keep["sigma_adj"] = sigma
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_adjoint(self._ctx, sigma.data_ptr(), _stream_ptr(self.device)))
+
+    def gradient(self):
+        B, n_t = self._keep.get("B", 1), self._keep.get("n_t", 1)
+        g = torch.empty((B, n_t, self.K), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_gradient(self._ctx, g.data_ptr(), _stream_ptr(self.device)))
+        return g
+
+    def cost_and_grad(self, u, rho0, sigma, dt, workspace=None):
+        """Phi[b] and dPhi/du[b] for a batch of control arrays."""
+        self.forward(u, rho0, dt, workspace=workspace)
+        phi = self.cost(sigma)
+        self.adjoint(sigma)
+        return phi, self.gradient()
+
+
+class OpenGrapeCost(torch.autograd.Function):
+    """Phi(u) = Tr(sigma rho_T(u)) as a differentiable torch function.
+
+    forward: og_forward + og_cost; backward: og_adjoint + og_gradient, which
+    must run in the exact mode (the first-order Eq. (13) gradient is not the
+    derivative of the computed Phi)."""
+
+    @staticmethod
+    def forward(ctx, u, problem, rho0, sigma, dt):
+        if problem.gmode != "exact":
+            raise ValueError("OpenGrapeCost needs a Problem created with gmode='exact'")
+        problem.forward(u.detach(), rho0, dt)
+        phi = problem.cost(sigma)
+        ctx.problem = problem
+        ctx.sigma = sigma
+        ctx.squeeze = u.dim() == 2
+        return phi[0] if ctx.squeeze else phi
+
+    @staticmethod
+    def backward(ctx, gphi):
+        ctx.problem.adjoint(ctx.sigma)
+        g = ctx.problem.gradient()
+        if ctx.squeeze:
+            return gphi * g[0], None, None, None, None
+        return gphi[:, None, None] * g, None, None, None, None
+
+
+def open_grape_cost(u, problem, rho0, sigma, dt):
+    return OpenGrapeCost.apply(u, problem, rho0, sigma, dt)

@@ -1,0 +1,1011 @@
+// Host side of the open-GRAPE library: operator preparation, workspace
+// layout, the forward / checkpoint / adjoint orchestration and the C ABI
+// declared in opengrape.h.
+//
+// Method (Boutin et al., Sec. III): rho is integrated slice by slice with
+// classical RK4 (Eq. (14)); lambda is integrated backward with L^dag from
+// sigma (Eqs. (11), (15)); the gradient of every slice is contracted from
+// the pair of states (Eq. (13)).  Every RK4 step is evaluated in the
+// nested (Horner) form
+//     Z1 = rho + h/4 L(rho),  Z2 = rho + h/3 L(Z1),  Z3 = rho + h/2 L(Z2),
+//     rho' = rho + h L(Z3),
+// which equals rho + h L rho + h^2/2 L^2 rho + h^3/6 L^3 rho + h^4/24 L^4 rho
+// exactly for the linear, slice-wise constant L, and needs one stage buffer
+// less than the k1..k4 form.
+//
+// Memory: forward states are stored every S = ckpt_stride slices (default
+// ceil(sqrt(N_t))); the backward sweep recomputes one segment of S states at
+// a time, so the workspace grows as sqrt(N_t) d^2, not N_t d^2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/opengrape.h"
+#include "og_device.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+og_status fail(og_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define OG_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(OG_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define OG_CHECK_LAUNCH()                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = hipGetLastError();                                                        \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(OG_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_));     \
+  } while (0)
+
+#define OG_TRY(expr)                 \
+  do {                               \
+    og_status s_ = (expr);           \
+    if (s_ != OG_OK) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Host-side operator algebra (float64 complex, row-major d x d)
+// ---------------------------------------------------------------------------
+struct Mat {
+  int d = 0;
+  std::vector<cd> a;
+  Mat() {}
+  explicit Mat(int n) : d(n), a((size_t)n * n, cd(0, 0)) {}
+  cd& operator()(int i, int j) { return a[(size_t)i * d + j]; }
+  cd operator()(int i, int j) const { return a[(size_t)i * d + j]; }
+};
+
+Mat from_ptr(const void* p, int d, size_t index) {
+  Mat m(d);
+  const double* x = static_cast<const double*>(p) + 2 * (size_t)d * d * index;
+  for (size_t e = 0; e < (size_t)d * d; ++e) m.a[e] = cd(x[2 * e], x[2 * e + 1]);
+  return m;
+}
+
+Mat dagger(const Mat& m) {
+  Mat r(m.d);
+  for (int i = 0; i < m.d; ++i)
+    for (int j = 0; j < m.d; ++j) r(i, j) = std::conj(m(j, i));
+  return r;
+}
+
+Mat matmul(const Mat& x, const Mat& y) {
+  Mat r(x.d);
+  for (int i = 0; i < x.d; ++i)
+    for (int k = 0; k < x.d; ++k) {
+      const cd v = x(i, k);
+      if (v == cd(0, 0)) continue;
+      for (int j = 0; j < x.d; ++j) r(i, j) += v * y(k, j);
+    }
+  return r;
+}
+
+Mat axpy(const Mat& x, cd s, const Mat& y) {  // x + s*y
+  Mat r = x;
+  for (size_t e = 0; e < r.a.size(); ++e) r.a[e] += s * y.a[e];
+  return r;
+}
+
+Mat scaled(cd s, const Mat& y) {
+  Mat r(y.d);
+  for (size_t e = 0; e < r.a.size(); ++e) r.a[e] = s * y.a[e];
+  return r;
+}
+
+Mat transpose(const Mat& m) {
+  Mat r(m.d);
+  for (int i = 0; i < m.d; ++i)
+    for (int j = 0; j < m.d; ++j) r(i, j) = m(j, i);
+  return r;
+}
+
+double herm_defect(const Mat& m) {
+  double worst = 0, scale = 0;
+  for (int i = 0; i < m.d; ++i)
+    for (int j = 0; j < m.d; ++j) {
+      worst = std::max(worst, std::abs(m(i, j) - std::conj(m(j, i))));
+      scale = std::max(scale, std::abs(m(i, j)));
+    }
+  return scale > 0 ? worst / scale : 0.0;
+}
+
+// Nonzero diagonals of m (offset o holds m[i, i + o]).
+void collect_offsets(const Mat& m, std::vector<int>& offs) {
+  for (int o = -(m.d - 1); o <= m.d - 1; ++o) {
+    bool nz = false;
+    for (int i = 0; i < m.d && !nz; ++i) {
+      const int j = i + o;
+      if (j >= 0 && j < m.d && m(i, j) != cd(0, 0)) nz = true;
+    }
+    if (nz && std::find(offs.begin(), offs.end(), o) == offs.end()) offs.push_back(o);
+  }
+  std::sort(offs.begin(), offs.end());
+}
+
+std::vector<cd> dia_values(const Mat& m, const std::vector<int>& offs, cd scale = cd(1, 0)) {
+  std::vector<cd> v(offs.size() * (size_t)m.d, cd(0, 0));
+  for (size_t t = 0; t < offs.size(); ++t)
+    for (int i = 0; i < m.d; ++i) {
+      const int j = i + offs[t];
+      if (j >= 0 && j < m.d) v[t * m.d + i] = scale * m(i, j);
+    }
+  return v;
+}
+
+// Upload a host complex128 vector converted to the working precision.
+template <typename T>
+og_status upload(const std::vector<cd>& h, og::cpx<T>** dptr) {
+  std::vector<og::cpx<T>> tmp(h.size());
+  for (size_t e = 0; e < h.size(); ++e) {
+    tmp[e].re = (T)h[e].real();
+    tmp[e].im = (T)h[e].imag();
+  }
+  const size_t bytes = std::max<size_t>(1, tmp.size()) * sizeof(og::cpx<T>);
+  OG_HIP(hipMalloc((void**)dptr, bytes));
+  if (!tmp.empty()) OG_HIP(hipMemcpy(*dptr, tmp.data(), tmp.size() * sizeof(og::cpx<T>), hipMemcpyHostToDevice));
+  return OG_OK;
+}
+
+std::vector<cd> concat(const std::vector<std::vector<cd>>& parts) {
+  std::vector<cd> r;
+  for (auto& p : parts) r.insert(r.end(), p.begin(), p.end());
+  return r;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// Operator data of one direction of propagation
+//   forward : A = G = -i H - 1/2 sum gamma c^dag c,  C_m = c_m
+//   adjoint : A = G^dag,                              C_m = c_m^dag
+// ---------------------------------------------------------------------------
+struct DirHost {
+  Mat A0;                 // u-independent part of A
+  std::vector<Mat> Ak;    // d A / d u_k
+  std::vector<Mat> C;     // collapse operators of this direction
+  std::vector<double> g;  // their rates
+};
+
+enum Dir { FWD = 0, ADJ = 1 };
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Engine (one per working precision)
+// ---------------------------------------------------------------------------
+struct EngineBase {
+  virtual ~EngineBase() {}
+  virtual size_t ws_bytes(int B, int n_t) const = 0;
+  virtual og_status forward(int B, int n_t, double dt, const double* u, const void* rho0, void* rhoT, void* ws,
+                            size_t ws_bytes, hipStream_t st) = 0;
+  virtual og_status cost(const void* sigma, double* phi, hipStream_t st) = 0;
+  virtual og_status adjoint(const void* sigma, hipStream_t st) = 0;
+  virtual og_status gradient(double* grad, hipStream_t st) = 0;
+};
+
+struct og_ctx {
+  int d = 0, K = 0, J = 0;
+  og_options opt{};
+  int path = OG_PATH_DENSE;
+  int phase = 0;  // 0: nothing, 1: forward done, 2: adjoint done
+  EngineBase* eng = nullptr;
+  // host data for the stability estimate
+  std::vector<double> h0_diag, h0_rad, hk_gersh, hk_frob;
+  double h0_frob = 0, diss_bound = 0;
+  int* status_dev = nullptr;
+  double* umax_dev = nullptr;
+};
+
+namespace {
+
+template <typename T>
+struct DirDev {
+  // banded
+  og::BandOps<T> band{};
+  og::cpx<T>* bA0 = nullptr;
+  og::cpx<T>* bAk = nullptr;
+  og::cpx<T>* bDl = nullptr;
+  og::cpx<T>* bDr = nullptr;
+  // dense
+  og::cpx<T>* A0 = nullptr;    // d x d
+  og::cpx<T>* Ak = nullptr;    // K x d x d
+  og::cpx<T>* C = nullptr;     // J x d x d
+  og::cpx<T>* Chat = nullptr;  // (J d) x d: rows m d .. : gamma_m / 2 * C_m^dag
+};
+
+template <typename T>
+struct Engine : EngineBase {
+  og_ctx* ctx;
+  int d, K, J;
+  bool banded;
+  long E;  // elements per matrix
+  DirDev<T> dir[2];
+  og::HBand<T> hband{};
+  og::cpx<T>* hHd = nullptr;   // banded H_k diagonals
+  og::cpx<T>* HT = nullptr;    // dense: transposes of H_k, K x d x d
+  int2* tiles = nullptr;
+  int ntile = 0;
+  static constexpr bool comp = sizeof(T) == 4;  // compensated states in float32
+
+  // evaluation state
+  int B = 0, n_t = 0, S = 1, n_seg = 0;
+  double dt = 0;
+  const double* u = nullptr;
+  // workspace views
+  og::cpx<T>*cur_hi, *cur_lo, *lam_hi, *lam_lo, *Za, *Zb;
+  og::cpx<T>*ck_hi, *ck_lo, *sg_hi, *sg_lo;
+  og::cpx<T>*Z1, *Z2, *Z3, *Zb1, *Zb2, *Zb3;
+  og::cpx<T>*st_hi, *st_lo;  // substep start states (EXACT, n_sub > 1)
+  og::cpx<T>*Aj[2], *X, *W, *Wp;
+  double* grad;
+
+  Engine(og_ctx* c) : ctx(c), d(c->d), K(c->K), J(c->J), banded(c->path == OG_PATH_BANDED), E((long)c->d * c->d) {}
+
+  ~Engine() override {
+    for (int s = 0; s < 2; ++s) {
+      void* ps[] = {dir[s].bA0, dir[s].bAk, dir[s].bDl, dir[s].bDr, dir[s].A0, dir[s].Ak, dir[s].C, dir[s].Chat};
+      for (void* p : ps)
+        if (p) (void)hipFree(p);
+    }
+    if (hHd) (void)hipFree(hHd);
+    if (HT) (void)hipFree(HT);
+    if (tiles) (void)hipFree(tiles);
+  }
+
+  og_status init(const DirHost host[2], const std::vector<Mat>& Hk) {
+    // upper-triangular tile list
+    const int nt = (d + og::TS - 1) / og::TS;
+    std::vector<int2> tl;
+    for (int i = 0; i < nt; ++i)
+      for (int j = i; j < nt; ++j) tl.push_back(make_int2(i, j));
+    ntile = (int)tl.size();
+    OG_HIP(hipMalloc((void**)&tiles, tl.size() * sizeof(int2)));
+    OG_HIP(hipMemcpy(tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice));
+    for (int s = 0; s < 2; ++s) {
+      const DirHost& h = host[s];
+      DirDev<T>& dv = dir[s];
+      if (banded) {
+        std::vector<int> offs;
+        collect_offsets(h.A0, offs);
+        for (auto& m : h.Ak) collect_offsets(m, offs);
+        if (offs.empty()) offs.push_back(0);
+        dv.band.nA = (int)offs.size();
+        for (size_t t = 0; t < offs.size(); ++t) dv.band.offA[t] = offs[t];
+        std::vector<std::vector<cd>> ak;
+        for (auto& m : h.Ak) ak.push_back(dia_values(m, offs));
+        OG_TRY(upload<T>(dia_values(h.A0, offs), &dv.bA0));
+        OG_TRY(upload<T>(concat(ak), &dv.bAk));
+        std::vector<std::vector<cd>> dl, dr;
+        int nD = 0;
+        for (size_t m = 0; m < h.C.size(); ++m) {
+          if (h.g[m] == 0.0) continue;
+          std::vector<int> co;
+          collect_offsets(h.C[m], co);
+          for (int p : co)
+            for (int q : co) {
+              dv.band.dp[nD] = p;
+              dv.band.dq[nD] = q;
+              std::vector<int> one_p{p}, one_q{q};
+              dl.push_back(dia_values(h.C[m], one_p, cd(h.g[m], 0)));
+              dr.push_back(dia_values(h.C[m], one_q));
+              ++nD;
+            }
+        }
+        dv.band.nD = nD;
+        OG_TRY(upload<T>(concat(dl), &dv.bDl));
+        OG_TRY(upload<T>(concat(dr), &dv.bDr));
+        dv.band.A0 = dv.bA0;
+        dv.band.Ak = dv.bAk;
+        dv.band.Dl = dv.bDl;
+        dv.band.Dr = dv.bDr;
+      } else {
+        OG_TRY(upload<T>(h.A0.a, &dv.A0));
+        std::vector<std::vector<cd>> ak, cc, ch;
+        for (auto& m : h.Ak) ak.push_back(m.a);
+        OG_TRY(upload<T>(concat(ak), &dv.Ak));
+        for (size_t m = 0; m < h.C.size(); ++m) {
+          cc.push_back(h.C[m].a);
+          ch.push_back(scaled(cd(0.5 * h.g[m], 0), dagger(h.C[m])).a);
+        }
+        OG_TRY(upload<T>(concat(cc), &dv.C));
+        OG_TRY(upload<T>(concat(ch), &dv.Chat));
+      }
+    }
+    if (banded) {
+      std::vector<int> offs;
+      for (auto& m : Hk) collect_offsets(m, offs);
+      if (offs.empty()) offs.push_back(0);
+      hband.nH = (int)offs.size();
+      for (size_t t = 0; t < offs.size(); ++t) hband.offH[t] = offs[t];
+      std::vector<std::vector<cd>> hv;
+      for (auto& m : Hk) hv.push_back(dia_values(m, offs));
+      OG_TRY(upload<T>(concat(hv), &hHd));
+      hband.Hd = hHd;
+    } else {
+      std::vector<std::vector<cd>> ht;
+      for (auto& m : Hk) ht.push_back(transpose(m).a);
+      OG_TRY(upload<T>(concat(ht), &HT));
+    }
+    return OG_OK;
+  }
+
+  // ----- workspace layout -----
+  struct Layout {
+    size_t off[32];
+    size_t total;
+  };
+  enum {
+    L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
+    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_GRAD, L_N
+  };
+
+  int stride_for(int nt) const {
+    int s = ctx->opt.ckpt_stride;
+    if (s <= 0) s = (int)std::ceil(std::sqrt((double)nt));
+    return std::max(1, std::min(s, nt));
+  }
+
+  Layout layout(int b, int nt) const {
+    Layout L{};
+    const int s = stride_for(nt);
+    const int nseg = (nt + s - 1) / s;
+    const size_t m = (size_t)b * E * sizeof(og::cpx<T>);  // one matrix per problem
+    const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
+    const int nsub = ctx->opt.n_sub;
+    size_t sz[L_N] = {};
+    sz[L_CUR_HI] = m;
+    sz[L_CUR_LO] = comp ? m : 0;
+    sz[L_LAM_HI] = m;
+    sz[L_LAM_LO] = comp ? m : 0;
+    sz[L_ZA] = m;
+    sz[L_ZB] = m;
+    sz[L_CK_HI] = (size_t)nseg * m;
+    sz[L_CK_LO] = comp ? (size_t)nseg * m : 0;
+    sz[L_SG_HI] = (size_t)(s + 1) * m;
+    sz[L_SG_LO] = comp ? (size_t)(s + 1) * m : 0;
+    if (exact) {
+      sz[L_Z1] = sz[L_Z2] = sz[L_Z3] = m;
+      sz[L_ZB1] = sz[L_ZB2] = sz[L_ZB3] = m;
+      sz[L_ST_HI] = (size_t)(nsub > 1 ? nsub - 1 : 0) * m;
+      sz[L_ST_LO] = comp ? sz[L_ST_HI] : 0;
+    }
+    if (!banded) {
+      sz[L_AJF] = m;
+      sz[L_AJA] = exact ? m : 0;
+      sz[L_X] = m;
+      sz[L_W] = (size_t)std::max(J, 1) * m;
+      sz[L_WP] = (exact ? 4 : 1) * m;
+    }
+    sz[L_GRAD] = (size_t)b * nt * std::max(K, 1) * sizeof(double);
+    size_t pos = 0;
+    for (int i = 0; i < L_N; ++i) {
+      L.off[i] = pos;
+      pos += align256(sz[i]);
+    }
+    L.total = pos;
+    return L;
+  }
+
+  size_t ws_bytes(int b, int nt) const override { return layout(b, nt).total; }
+
+  // ----- launch helpers -----
+  hipStream_t st = nullptr;
+
+  dim3 stage_grid() const { return dim3((unsigned)(B * ntile)); }
+
+  og::StageIO<T> io_base() const {
+    og::StageIO<T> io{};
+    io.in_s = E;
+    io.s_s = E;
+    io.o_s = E;
+    io.ex_s = E;
+    io.status = ctx->status_dev;
+    return io;
+  }
+
+  // One Runge-Kutta stage for the whole batch: out = f(L_dir(in)).
+  og_status stage(int dr, int mode, int jslice, const og::cpx<T>* in, const og::cpx<T>* shi,
+                  const og::cpx<T>* slo, og::cpx<T>* ohi, og::cpx<T>* olo, T coef,
+                  const og::cpx<T>* ex0 = nullptr, const og::cpx<T>* ex1 = nullptr,
+                  const og::cpx<T>* ex2 = nullptr) {
+    og::StageIO<T> io = io_base();
+    io.in = in;
+    io.shi = shi;
+    io.slo = slo;
+    io.ohi = ohi;
+    io.olo = olo;
+    io.coef = coef;
+    io.ex[0] = ex0;
+    io.ex[1] = ex1;
+    io.ex[2] = ex2;
+    io.nex = ex2 ? 3 : (ex1 ? 2 : (ex0 ? 1 : 0));
+    const long u_bs = (long)n_t * K;
+    if (banded) {
+      const og::BandOps<T>& ops = dir[dr].band;
+      if (mode == og::SM_STAGE)
+        og::band_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, K, u, u_bs, jslice);
+      else if (mode == og::SM_FINAL)
+        og::band_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, K, u, u_bs, jslice);
+      else
+        og::band_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, K, u, u_bs, jslice);
+      OG_CHECK_LAUNCH();
+      return OG_OK;
+    }
+    // dense: X = A_j in + 1/2 sum gamma C (C in)^dag ... via two GEMMs, then X + X^dag
+    const DirDev<T>& dv = dir[dr];
+    og::GemmArgs<T> g{};
+    g.nm = 1 + J;
+    g.M = g.N = g.Kd = d;
+    g.alpha.re = 1;
+    g.alpha.im = 0;
+    g.beta.re = 0;
+    g.beta.im = 0;
+    g.A[0] = Aj[dr];
+    g.sA[0] = E;
+    g.lda[0] = d;
+    g.C[0] = X;
+    g.sC[0] = E;
+    g.ldc[0] = d;
+    for (int m = 1; m <= J; ++m) {
+      g.A[m] = dv.C + (long)(m - 1) * E;
+      g.sA[m] = 0;
+      g.lda[m] = d;
+      g.C[m] = W + (long)(m - 1) * d;
+      g.sC[m] = (long)J * E;
+      g.ldc[m] = J * d;
+    }
+    for (int m = 0; m <= J; ++m) {
+      g.B[m] = in;
+      g.sB[m] = E;
+      g.ldb[m] = d;
+    }
+    const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * g.nm));
+    og::zgemm_kernel<T><<<gg, 256, 0, st>>>(g);
+    OG_CHECK_LAUNCH();
+    if (J > 0) {
+      og::GemmArgs<T> h{};
+      h.nm = 1;
+      h.M = d;
+      h.N = d;
+      h.Kd = J * d;
+      h.alpha.re = 1;
+      h.beta.re = 1;
+      h.A[0] = W;
+      h.sA[0] = (long)J * E;
+      h.lda[0] = J * d;
+      h.B[0] = dv.Chat;
+      h.sB[0] = 0;
+      h.ldb[0] = d;
+      h.C[0] = X;
+      h.sC[0] = E;
+      h.ldc[0] = d;
+      const dim3 hg((d + 63) / 64, (d + 63) / 64, (unsigned)B);
+      og::zgemm_kernel<T><<<hg, 256, 0, st>>>(h);
+      OG_CHECK_LAUNCH();
+    }
+    if (mode == og::SM_STAGE)
+      og::dense_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(X, E, io, tiles, ntile, d);
+    else if (mode == og::SM_FINAL)
+      og::dense_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(X, E, io, tiles, ntile, d);
+    else
+      og::dense_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(X, E, io, tiles, ntile, d);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
+  og_status assemble(int dr, int jslice) {
+    if (banded) return OG_OK;
+    const DirDev<T>& dv = dir[dr];
+    const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
+    og::assemble_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(dv.A0, dv.Ak, K, E, u, (long)n_t * K, jslice, Aj[dr]);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
+  // n_sub RK4 steps of slice j in direction dr: (in) -> (out); in == out allowed.
+  og_status rk_slice(int dr, int jslice, const og::cpx<T>* ihi, const og::cpx<T>* ilo, og::cpx<T>* ohi,
+                     og::cpx<T>* olo) {
+    const int nsub = ctx->opt.n_sub;
+    const T h = (T)(dt / nsub);
+    OG_TRY(assemble(dr, jslice));
+    for (int s = 0; s < nsub; ++s) {
+      const og::cpx<T>* shi = s == 0 ? ihi : ohi;
+      const og::cpx<T>* slo = s == 0 ? ilo : olo;
+      OG_TRY(stage(dr, og::SM_STAGE, jslice, shi, shi, slo, Za, nullptr, h / T(4)));
+      OG_TRY(stage(dr, og::SM_STAGE, jslice, Za, shi, slo, Zb, nullptr, h / T(3)));
+      OG_TRY(stage(dr, og::SM_STAGE, jslice, Zb, shi, slo, Za, nullptr, h / T(2)));
+      OG_TRY(stage(dr, og::SM_FINAL, jslice, Za, shi, slo, ohi, olo, h));
+    }
+    return OG_OK;
+  }
+
+  // g[:, j, :] (+)= sum_p coef_p * 2 Im Tr(H_k X_p L_p)
+  og_status contract(int jslice, int np, const og::cpx<T>* const* Xs, const og::cpx<T>* const* Ls,
+                     const double* coefs, int accumulate) {
+    if (K == 0) return OG_OK;
+    const long g_bs = (long)n_t * K;
+    if (banded) {
+      og::PairArgs<T> pa{};
+      pa.np = np;
+      pa.x_s = E;
+      pa.l_s = E;
+      for (int p = 0; p < np; ++p) {
+        pa.X[p] = Xs[p];
+        pa.L[p] = Ls[p];
+        pa.coef[p] = coefs[p];
+      }
+      og::band_contract_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(pa, hband, K, d, grad, g_bs, jslice, accumulate);
+      OG_CHECK_LAUNCH();
+      return OG_OK;
+    }
+    // dense: W_p = X_p L_p for every pair, then the Frobenius products
+    og::GemmArgs<T> g{};
+    g.nm = np;
+    g.M = g.N = g.Kd = d;
+    g.alpha.re = 1;
+    for (int p = 0; p < np; ++p) {
+      g.A[p] = Xs[p];
+      g.sA[p] = E;
+      g.lda[p] = d;
+      g.B[p] = Ls[p];
+      g.sB[p] = E;
+      g.ldb[p] = d;
+      g.C[p] = Wp + (long)p * E;
+      g.sC[p] = (long)np * E;
+      g.ldc[p] = d;
+    }
+    const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * np));
+    og::zgemm_kernel<T><<<gg, 256, 0, st>>>(g);
+    OG_CHECK_LAUNCH();
+    double c[4] = {0, 0, 0, 0};
+    for (int p = 0; p < np; ++p) c[p] = coefs[p];
+    og::dense_contract_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(Wp, E, (long)np * E, np, c[0], c[1], c[2], c[3],
+                                                                   HT, K, E, grad, g_bs, jslice, accumulate);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
+  og::cpx<T>* slot(og::cpx<T>* base, int idx) const { return base ? base + (long)idx * B * E : nullptr; }
+
+  og_status bind(void* ws, int b, int nt) {
+    const Layout L = layout(b, nt);
+    char* p = static_cast<char*>(ws);
+    auto at = [&](int i) { return reinterpret_cast<og::cpx<T>*>(p + L.off[i]); };
+    auto opt_at = [&](int i, bool use) { return use ? at(i) : nullptr; };
+    const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
+    cur_hi = at(L_CUR_HI);
+    cur_lo = opt_at(L_CUR_LO, comp);
+    lam_hi = at(L_LAM_HI);
+    lam_lo = opt_at(L_LAM_LO, comp);
+    Za = at(L_ZA);
+    Zb = at(L_ZB);
+    ck_hi = at(L_CK_HI);
+    ck_lo = opt_at(L_CK_LO, comp);
+    sg_hi = at(L_SG_HI);
+    sg_lo = opt_at(L_SG_LO, comp);
+    Z1 = opt_at(L_Z1, exact);
+    Z2 = opt_at(L_Z2, exact);
+    Z3 = opt_at(L_Z3, exact);
+    Zb1 = opt_at(L_ZB1, exact);
+    Zb2 = opt_at(L_ZB2, exact);
+    Zb3 = opt_at(L_ZB3, exact);
+    st_hi = opt_at(L_ST_HI, exact && ctx->opt.n_sub > 1);
+    st_lo = opt_at(L_ST_LO, exact && ctx->opt.n_sub > 1 && comp);
+    Aj[0] = opt_at(L_AJF, !banded);
+    Aj[1] = opt_at(L_AJA, !banded && exact);
+    if (!banded && !exact) Aj[1] = Aj[0];
+    X = opt_at(L_X, !banded);
+    W = opt_at(L_W, !banded);
+    Wp = opt_at(L_WP, !banded);
+    grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);
+    return OG_OK;
+  }
+
+  og_status copy_state(og::cpx<T>* dhi, og::cpx<T>* dlo, const og::cpx<T>* shi, const og::cpx<T>* slo) {
+    const size_t bytes = (size_t)B * E * sizeof(og::cpx<T>);
+    OG_HIP(hipMemcpyAsync(dhi, shi, bytes, hipMemcpyDeviceToDevice, st));
+    if (comp) OG_HIP(hipMemcpyAsync(dlo, slo, bytes, hipMemcpyDeviceToDevice, st));
+    return OG_OK;
+  }
+
+  og_status load(const void* src, long src_s, og::cpx<T>* hi, og::cpx<T>* lo) {
+    const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
+    og::load_state_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(static_cast<const double*>(src), src_s, E, hi, lo, E);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
+  og_status forward(int b, int nt, double dt_, const double* u_, const void* rho0, void* rhoT, void* ws,
+                    size_t wsb, hipStream_t s) override {
+    if (wsb < ws_bytes(b, nt)) return fail(OG_ERR_WORKSPACE, "workspace smaller than og_workspace_bytes()");
+    st = s;
+    B = b;
+    n_t = nt;
+    dt = dt_;
+    u = u_;
+    S = stride_for(nt);
+    n_seg = (nt + S - 1) / S;
+    OG_TRY(bind(ws, b, nt));
+    OG_TRY(load(rho0, E, cur_hi, cur_lo));
+    for (int j = 0; j < n_t; ++j) {
+      if (j % S == 0) OG_TRY(copy_state(slot(ck_hi, j / S), slot(ck_lo, j / S), cur_hi, cur_lo));
+      OG_TRY(rk_slice(FWD, j, cur_hi, cur_lo, cur_hi, cur_lo));
+    }
+    if (rhoT) {
+      const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
+      og::store_state_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(cur_hi, cur_lo, E, E, static_cast<double*>(rhoT));
+      OG_CHECK_LAUNCH();
+    }
+    return OG_OK;
+  }
+
+  og_status cost(const void* sigma, double* phi, hipStream_t s) override {
+    og::cost_kernel<T><<<dim3((unsigned)B), 256, 0, s>>>(static_cast<const double*>(sigma), cur_hi, cur_lo, E, E, phi);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
+  og_status adjoint(const void* sigma, hipStream_t s) override {
+    st = s;
+    const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
+    const int nsub = ctx->opt.n_sub;
+    const T h = (T)(dt / nsub);
+    OG_TRY(load(sigma, 0, lam_hi, lam_lo));
+    for (int seg = n_seg - 1; seg >= 0; --seg) {
+      const int j0 = seg * S, j1 = std::min(n_t, j0 + S), n = j1 - j0;
+      OG_TRY(copy_state(slot(sg_hi, 0), slot(sg_lo, 0), slot(ck_hi, seg), slot(ck_lo, seg)));
+      for (int jj = 0; jj < n; ++jj)
+        OG_TRY(rk_slice(FWD, j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1), slot(sg_lo, jj + 1)));
+      for (int jj = n - 1; jj >= 0; --jj) {
+        const int j = j0 + jj;
+        if (!exact) {
+          const og::cpx<T>* Xs[1] = {slot(sg_hi, jj + 1)};
+          const og::cpx<T>* Ls[1] = {lam_hi};
+          const double cf[1] = {dt};
+          OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
+          OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
+          continue;
+        }
+        // exact derivative of the RK4-discretised Phi: reverse through the
+        // nested stages Z1..Z3 of every substep of slice j.
+        OG_TRY(assemble(FWD, j));
+        OG_TRY(assemble(ADJ, j));
+        for (int sub = 1; sub < nsub; ++sub) {
+          const og::cpx<T>* phi_ = sub == 1 ? slot(sg_hi, jj) : slot(st_hi, sub - 2);
+          const og::cpx<T>* plo = sub == 1 ? slot(sg_lo, jj) : slot(st_lo, sub - 2);
+          og::cpx<T>* ohi = slot(st_hi, sub - 1);
+          og::cpx<T>* olo = slot(st_lo, sub - 1);
+          OG_TRY(stage(FWD, og::SM_STAGE, j, phi_, phi_, plo, Za, nullptr, h / T(4)));
+          OG_TRY(stage(FWD, og::SM_STAGE, j, Za, phi_, plo, Zb, nullptr, h / T(3)));
+          OG_TRY(stage(FWD, og::SM_STAGE, j, Zb, phi_, plo, Za, nullptr, h / T(2)));
+          OG_TRY(stage(FWD, og::SM_FINAL, j, Za, phi_, plo, ohi, olo, h));
+        }
+        for (int sub = nsub - 1; sub >= 0; --sub) {
+          const og::cpx<T>* s_hi = sub == 0 ? slot(sg_hi, jj) : slot(st_hi, sub - 1);
+          const og::cpx<T>* s_lo = sub == 0 ? slot(sg_lo, jj) : slot(st_lo, sub - 1);
+          OG_TRY(stage(FWD, og::SM_STAGE, j, s_hi, s_hi, s_lo, Z1, nullptr, h / T(4)));
+          OG_TRY(stage(FWD, og::SM_STAGE, j, Z1, s_hi, s_lo, Z2, nullptr, h / T(3)));
+          OG_TRY(stage(FWD, og::SM_STAGE, j, Z2, s_hi, s_lo, Z3, nullptr, h / T(2)));
+          OG_TRY(stage(ADJ, og::SM_SCALE, j, lam_hi, nullptr, nullptr, Zb3, nullptr, h));
+          OG_TRY(stage(ADJ, og::SM_SCALE, j, Zb3, nullptr, nullptr, Zb2, nullptr, h / T(2)));
+          OG_TRY(stage(ADJ, og::SM_SCALE, j, Zb2, nullptr, nullptr, Zb1, nullptr, h / T(3)));
+          const og::cpx<T>* Xs[4] = {Z3, Z2, Z1, s_hi};
+          const og::cpx<T>* Ls[4] = {lam_hi, Zb3, Zb2, Zb1};
+          const double hd = dt / nsub;
+          const double cf[4] = {hd, hd / 2, hd / 3, hd / 4};
+          OG_TRY(contract(j, 4, Xs, Ls, cf, sub != nsub - 1));
+          OG_TRY(stage(ADJ, og::SM_FINAL, j, Zb1, lam_hi, lam_lo, lam_hi, lam_lo, h / T(4), Zb1, Zb2, Zb3));
+        }
+      }
+    }
+    return OG_OK;
+  }
+
+  og_status gradient(double* out, hipStream_t s) override {
+    OG_HIP(hipMemcpyAsync(out, grad, (size_t)B * n_t * K * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return OG_OK;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void og_default_options(og_options* opt) {
+  if (!opt) return;
+  opt->prec = OG_F64;
+  opt->gmode = OG_GRAD_GRAPE1;
+  opt->path = OG_PATH_AUTO;
+  opt->n_sub = 1;
+  opt->ckpt_stride = 0;
+  opt->validate = 1;
+}
+
+const char* og_status_string(og_status s) {
+  switch (s) {
+    case OG_OK: return "ok";
+    case OG_ERR_ARG: return "invalid argument";
+    case OG_ERR_SHAPE: return "unsupported shape or operator structure";
+    case OG_ERR_NOT_HERMITIAN: return "operator is not Hermitian";
+    case OG_ERR_UNSTABLE_DT: return "time step outside the RK4 stability bound";
+    case OG_ERR_WORKSPACE: return "workspace missing or too small";
+    case OG_ERR_ORDER: return "call out of order";
+    case OG_ERR_NONFINITE: return "non-finite state";
+    case OG_ERR_DEVICE: return "HIP device error";
+  }
+  return "unknown status";
+}
+
+const char* og_last_error(void) { return g_err.c_str(); }
+
+int og_path_used(const og_ctx* ctx) { return ctx ? ctx->path : -1; }
+
+og_status og_create(og_ctx** out, int d, int K, int J, const void* H0p, const void* Hkp, const void* cp,
+                    const double* gamma, const og_options* optp) {
+  g_err.clear();
+  if (!out) return fail(OG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > 4096) return fail(OG_ERR_ARG, "d must be in [1, 4096]");
+  if (K < 0 || K > og::MAXK) return fail(OG_ERR_ARG, "K must be in [0, 16]");
+  if (J < 0 || J > 16) return fail(OG_ERR_ARG, "J must be in [0, 16]");
+  if (!H0p) return fail(OG_ERR_ARG, "H0 is NULL");
+  if (K > 0 && !Hkp) return fail(OG_ERR_ARG, "Hk is NULL with K > 0");
+  if (J > 0 && (!cp || !gamma)) return fail(OG_ERR_ARG, "c_ops or gamma is NULL with J > 0");
+  og_options opt;
+  og_default_options(&opt);
+  if (optp) opt = *optp;
+  if (opt.prec != OG_F64 && opt.prec != OG_F32) return fail(OG_ERR_ARG, "unknown precision");
+  if (opt.gmode != OG_GRAD_GRAPE1 && opt.gmode != OG_GRAD_EXACT) return fail(OG_ERR_ARG, "unknown gradient mode");
+  if (opt.path < OG_PATH_AUTO || opt.path > OG_PATH_BANDED) return fail(OG_ERR_ARG, "unknown path");
+  if (opt.n_sub < 1 || opt.n_sub > 64) return fail(OG_ERR_ARG, "n_sub must be in [1, 64]");
+  if (opt.ckpt_stride < 0) return fail(OG_ERR_ARG, "ckpt_stride must be >= 0");
+  for (int m = 0; m < J; ++m)
+    if (!(gamma[m] >= 0.0) || !std::isfinite(gamma[m])) return fail(OG_ERR_ARG, "rates must be finite and >= 0");
+
+  Mat H0 = from_ptr(H0p, d, 0);
+  std::vector<Mat> Hk, C;
+  for (int k = 0; k < K; ++k) Hk.push_back(from_ptr(Hkp, d, k));
+  for (int m = 0; m < J; ++m) C.push_back(from_ptr(cp, d, m));
+  for (auto* mp : {&H0})
+    for (auto& z : mp->a)
+      if (!std::isfinite(z.real()) || !std::isfinite(z.imag())) return fail(OG_ERR_ARG, "non-finite operator entry");
+  if (opt.validate) {
+    if (herm_defect(H0) > 1e-12) return fail(OG_ERR_NOT_HERMITIAN, "H0 is not Hermitian");
+    for (int k = 0; k < K; ++k)
+      if (herm_defect(Hk[k]) > 1e-12) return fail(OG_ERR_NOT_HERMITIAN, "H_" + std::to_string(k) + " is not Hermitian");
+  }
+
+  // G0 = -i H0 - 1/2 sum_m gamma_m c_m^dag c_m (Eq. (4) folded into the generator)
+  const cd mi(0, -1);
+  Mat G0 = scaled(mi, H0);
+  std::vector<Mat> cdc;
+  for (int m = 0; m < J; ++m) {
+    cdc.push_back(matmul(dagger(C[m]), C[m]));
+    G0 = axpy(G0, cd(-0.5 * gamma[m], 0), cdc.back());
+  }
+  DirHost host[2];
+  host[FWD].A0 = G0;
+  host[ADJ].A0 = dagger(G0);
+  for (int k = 0; k < K; ++k) {
+    host[FWD].Ak.push_back(scaled(mi, Hk[k]));
+    host[ADJ].Ak.push_back(scaled(cd(0, 1), Hk[k]));
+  }
+  for (int m = 0; m < J; ++m) {
+    host[FWD].C.push_back(C[m]);
+    host[ADJ].C.push_back(dagger(C[m]));
+    host[FWD].g.push_back(gamma[m]);
+    host[ADJ].g.push_back(gamma[m]);
+  }
+
+  // decide the path: diagonal storage when every operator set has few diagonals
+  int nA = 0, nD = 0, nH = 0;
+  {
+    std::vector<int> offs;
+    collect_offsets(G0, offs);
+    for (auto& m : Hk) collect_offsets(m, offs);
+    nA = (int)offs.size();
+    for (int m = 0; m < J; ++m) {
+      if (gamma[m] == 0.0) continue;
+      std::vector<int> co;
+      collect_offsets(C[m], co);
+      nD += (int)(co.size() * co.size());
+    }
+    std::vector<int> ho;
+    for (auto& m : Hk) collect_offsets(m, ho);
+    nH = (int)ho.size();
+  }
+  const bool band_ok = nA <= og::MAXA && nD <= og::MAXD && nH <= og::MAXH;
+  int path = opt.path;
+  if (path == OG_PATH_BANDED && !band_ok)
+    return fail(OG_ERR_SHAPE, "operators have too many diagonals for the banded path (nA=" + std::to_string(nA) +
+                                  ", nD=" + std::to_string(nD) + ", nH=" + std::to_string(nH) + ")");
+  if (path == OG_PATH_AUTO) path = (band_ok && 2 * nA + nD <= std::max(8, d / 2)) ? OG_PATH_BANDED : OG_PATH_DENSE;
+
+  og_ctx* ctx = new og_ctx();
+  ctx->d = d;
+  ctx->K = K;
+  ctx->J = J;
+  ctx->opt = opt;
+  ctx->path = path;
+  // Gershgorin data for the stability estimate
+  ctx->h0_diag.resize(d);
+  ctx->h0_rad.resize(d);
+  for (int i = 0; i < d; ++i) {
+    double r = 0;
+    for (int j = 0; j < d; ++j)
+      if (j != i) r += std::abs(H0(i, j));
+    ctx->h0_diag[i] = H0(i, i).real();
+    ctx->h0_rad[i] = r;
+  }
+  ctx->hk_gersh.assign((size_t)K * d, 0.0);
+  ctx->hk_frob.assign(K, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < d; ++i) {
+      double r = 0;
+      for (int j = 0; j < d; ++j) {
+        r += std::abs(Hk[k](i, j));
+        ctx->hk_frob[k] += std::norm(Hk[k](i, j));
+      }
+      ctx->hk_gersh[(size_t)k * d + i] = r;
+    }
+  for (int k = 0; k < K; ++k) ctx->hk_frob[k] = std::sqrt(ctx->hk_frob[k]);
+  for (auto& z : H0.a) ctx->h0_frob += std::norm(z);
+  ctx->h0_frob = std::sqrt(ctx->h0_frob);
+  for (int m = 0; m < J; ++m) {
+    double worst = 0;
+    for (int i = 0; i < d; ++i) {
+      double r = 0;
+      for (int j = 0; j < d; ++j) r += std::abs(cdc[m](i, j));
+      worst = std::max(worst, r);
+    }
+    ctx->diss_bound += 2.0 * gamma[m] * worst;
+  }
+
+  hipError_t e1 = hipMalloc((void**)&ctx->status_dev, 256);
+  hipError_t e2 = hipMalloc((void**)&ctx->umax_dev, 256);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    og_destroy(ctx);
+    return fail(OG_ERR_DEVICE, "hipMalloc of context scratch failed");
+  }
+  if (hipMemset(ctx->status_dev, 0, 256) != hipSuccess) {
+    og_destroy(ctx);
+    return fail(OG_ERR_DEVICE, "hipMemset failed");
+  }
+  og_status s;
+  if (opt.prec == OG_F64) {
+    auto* e = new Engine<double>(ctx);
+    ctx->eng = e;
+    s = e->init(host, Hk);
+  } else {
+    auto* e = new Engine<float>(ctx);
+    ctx->eng = e;
+    s = e->init(host, Hk);
+  }
+  if (s != OG_OK) {
+    std::string keep = g_err;
+    og_destroy(ctx);
+    g_err = keep;
+    return s;
+  }
+  *out = ctx;
+  return OG_OK;
+}
+
+og_status og_destroy(og_ctx* ctx) {
+  if (!ctx) return OG_OK;
+  (void)hipDeviceSynchronize();
+  delete ctx->eng;
+  if (ctx->status_dev) (void)hipFree(ctx->status_dev);
+  if (ctx->umax_dev) (void)hipFree(ctx->umax_dev);
+  delete ctx;
+  return OG_OK;
+}
+
+size_t og_workspace_bytes(const og_ctx* ctx, int B, int n_t) {
+  if (!ctx || !ctx->eng || B < 1 || n_t < 1) return 0;
+  return ctx->eng->ws_bytes(B, n_t);
+}
+
+og_status og_forward(og_ctx* ctx, int B, int n_t, double dt, const double* u, const void* rho0, void* rhoT,
+                     void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (B < 1 || B > (1 << 20)) return fail(OG_ERR_ARG, "B must be >= 1");
+  if (n_t < 1) return fail(OG_ERR_ARG, "n_t must be >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(OG_ERR_ARG, "dt must be finite and > 0");
+  if ((ctx->K > 0 && !u) || !rho0) return fail(OG_ERR_ARG, "u or rho0 is NULL");
+  if (!ws) return fail(OG_ERR_WORKSPACE, "workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(OG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int K = ctx->K, d = ctx->d;
+  ctx->phase = 0;
+  OG_HIP(hipMemsetAsync(ctx->status_dev, 0, sizeof(int), st));
+  if (ctx->opt.validate && K > 0) {
+    og::umax_kernel<<<1, 256, 0, st>>>(u, (long)B * n_t, K, ctx->umax_dev);
+    OG_CHECK_LAUNCH();
+    std::vector<double> um(K);
+    OG_HIP(hipMemcpyAsync(um.data(), ctx->umax_dev, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    OG_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < K; ++k)
+      if (!std::isfinite(um[k])) return fail(OG_ERR_ARG, "non-finite control");
+    double hi = -1e300, lo = 1e300, frob = ctx->h0_frob;
+    for (int i = 0; i < d; ++i) {
+      double r = ctx->h0_rad[i];
+      for (int k = 0; k < K; ++k) r += um[k] * ctx->hk_gersh[(size_t)k * d + i];
+      hi = std::max(hi, ctx->h0_diag[i] + r);
+      lo = std::min(lo, ctx->h0_diag[i] - r);
+    }
+    for (int k = 0; k < K; ++k) frob += um[k] * ctx->hk_frob[k];
+    const double span = std::min(hi - lo, 2.0 * frob);
+    const double h = dt / ctx->opt.n_sub;
+    if (h * span > 2.83 || h * ctx->diss_bound > 2.78) {
+      char buf[256];
+      snprintf(buf, sizeof buf,
+               "RK4 step h=%g outside the stability bound: h*span(H)=%.3f (limit 2.83), h*dissipation=%.3f (limit "
+               "2.78); raise n_sub",
+               h, h * span, h * ctx->diss_bound);
+      return fail(OG_ERR_UNSTABLE_DT, buf);
+    }
+  } else {
+    (void)d;
+  }
+  OG_TRY(ctx->eng->forward(B, n_t, dt, u, rho0, rhoT, ws, ws_bytes, st));
+  ctx->phase = 1;
+  return OG_OK;
+}
+
+og_status og_cost(og_ctx* ctx, const void* sigma, double* phi, void* stream) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (!sigma || !phi) return fail(OG_ERR_ARG, "sigma or phi is NULL");
+  if (ctx->phase < 1) return fail(OG_ERR_ORDER, "og_cost before og_forward");
+  return ctx->eng->cost(sigma, phi, static_cast<hipStream_t>(stream));
+}
+
+og_status og_adjoint(og_ctx* ctx, const void* sigma, void* stream) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (!sigma) return fail(OG_ERR_ARG, "sigma is NULL");
+  if (ctx->phase < 1) return fail(OG_ERR_ORDER, "og_adjoint before og_forward");
+  OG_TRY(ctx->eng->adjoint(sigma, static_cast<hipStream_t>(stream)));
+  ctx->phase = 2;
+  return OG_OK;
+}
+
+og_status og_gradient(og_ctx* ctx, double* grad, void* stream) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (!grad) return fail(OG_ERR_ARG, "grad is NULL");
+  if (ctx->phase < 2) return fail(OG_ERR_ORDER, "og_gradient before og_adjoint");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  OG_TRY(ctx->eng->gradient(grad, st));
+  if (ctx->opt.validate) {
+    int flag = 0;
+    OG_HIP(hipMemcpyAsync(&flag, ctx->status_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    OG_HIP(hipStreamSynchronize(st));
+    if (flag) return fail(OG_ERR_NONFINITE, "a propagated state became non-finite");
+  }
+  return OG_OK;
+}
+
+}  // extern "C"
