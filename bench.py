@@ -1,0 +1,238 @@
+"""Benchmark: gradient evaluations per second of exponential-free open GRAPE.
+
+Workload (one "step"): forward RK4 sweep, cost, backward adjoint sweep with
+segment recompute, and the per-slice gradient, for a batch of B independent
+control arrays on the transmon(3) x resonator(80) model: d = 240, K = 4
+controls (resonator and qubit I/Q), J = 3 collapse operators, N_t = 10000
+slices of dt = 0.002/kappa, smooth Gaussian-filtered noise controls
+(problem b uses seed 2 + b), sqrt(N_t) checkpoints.  float32 is the
+headline; the same workload is timed in float64 for the FP32-vs-FP64
+comparison.  Inputs are generated on the host and resident in HBM before the
+timed region starts.
+
+Prints one JSON line (rank 0).  With no flags: N = 1 GPU, 1 warmup step, 2
+timed steps per precision, plus the CPU oracle baseline on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "gradient evals/s at d=240 FP32 vs FP64 (≤1e-5 err); served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--n-t", type=int, default=10000)
+    ap.add_argument("--gmode", default="grape1", choices=["grape1", "exact"])
+    ap.add_argument("--path", default="banded", choices=["banded", "dense", "auto"])
+    ap.add_argument("--precisions", default="f32,f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slices", type=int, default=60, help="slices of the CPU oracle sample")
+    ap.add_argument("--profile-every", type=int, default=97)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes 5 times (for scaling HBM counters)")
+    return ap.parse_args()
+
+
+def copy_probe(nbytes):
+    """A plain copy kernel of known size: each launch reads and writes nbytes."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": 5}), flush=True)
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(args, prec, w, golden):
+    import torch
+
+    from paper_1609_03170_amd import Problem
+
+    dev = torch.device("cuda", 0)
+    B, n_t = args.batch, args.n_t
+    p = Problem.from_workload(w, prec=prec, path=args.path, gmode=args.gmode)
+    u = torch.tensor(np.ascontiguousarray(w.u.reshape(B, n_t, w.K)), device=dev)
+    rho0 = torch.tensor(np.broadcast_to(w.rho0, (B, w.d, w.d)).copy(), device=dev)
+    sigma = torch.tensor(w.sigma, device=dev)
+    ws = torch.empty(p.workspace_bytes(B, n_t), dtype=torch.uint8, device=dev)
+    _log(f"[bench] {prec} B={B} N_t={n_t} path={p.path} workspace={ws.numel() / 2**30:.2f} GiB")
+
+    def step():
+        phi, g = p.cost_and_grad(u, rho0, sigma, w.dt, workspace=ws)
+        return phi, g
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        _log(f"[bench] {prec} warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    p.profile(args.profile_every)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        phi, g = step()
+        torch.cuda.synchronize()
+        _log(f"[bench] {prec} step {i + 1}/{args.steps} done ({time.perf_counter() - t0:.2f} s)")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_us, kern_n = p.profile_read()
+    p.profile(0)
+    phi = phi.cpu().numpy()
+    g = g.cpu().numpy()
+    out = dict(prec=prec, elapsed=elapsed, ms_per_step=1000 * elapsed / args.steps,
+               value=B * args.steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path)
+    if golden is not None and n_t == 10000:
+        gkey = "g_grape1" if args.gmode == "grape1" else "g_exact"
+        out["err_phi"] = float(abs(phi[0] - golden["phi"]) / abs(golden["phi"]))
+        out["err_grad"] = float(np.linalg.norm(g[0] - golden[gkey]) / np.linalg.norm(golden[gkey]))
+    p.close()
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def measured_traffic(prec, batch, path):
+    """HBM bytes per launch of the stage kernel from the committed rocprofv3
+    counter summary, or None when there is none for this configuration or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+
+    if prec != "f32" or batch != 128 or path != "banded":
+        return None
+    summary = os.path.join(ROOT, "profiles", "band_stage_kernel_transmon240_b128_f32.md")
+    src = os.path.join(ROOT, "paper_1609_03170_amd", "csrc", "og_device.h")
+    if not os.path.exists(summary):
+        return None
+    fields = {}
+    for line in open(summary):
+        if ":" in line and not line.startswith((" ", "|", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("source-sha256-16") != sha:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(args, w):
+    """The float64 oracle on the host cores, on a bounded sample: the first
+    args.cpu_slices slices of problem 0 (forward + backward + first-order
+    gradient), scaled to one full gradient evaluation."""
+    import resource
+
+    from oracle import rk
+
+    n = args.cpu_slices
+    u = w.u.reshape(args.batch, args.n_t, w.K)[0, :n]
+    m = rk.Model.from_workload(w, sparse=True)
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    rhos = rk.forward(m, u, w.rho0, w.dt)
+    lams = rk.backward(m, u, w.sigma, w.dt)
+    rk.gradient_grape1(m, u, rhos, lams, w.dt)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    per_eval = wall * args.n_t / n
+    return {"value": 1.0 / per_eval, "unit": "grad-evals/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"float64 NumPy/SciPy-sparse oracle, problem 0, first {n} of {args.n_t} slices "
+                      f"(forward + backward + Eq. (13) gradient) in {wall:.1f} s, scaled x{args.n_t / n:.0f}"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the path has no multi-GPU component here); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    import workloads as wl
+
+    _log(f"[bench] generating inputs B={args.batch} N_t={args.n_t}")
+    w = wl.config_c3(batch=args.batch, n_t=args.n_t)
+    gpath = os.path.join(ROOT, "tests", "golden", "c3_cqed_d240.npz")
+    golden = dict(np.load(gpath)) if os.path.exists(gpath) else None
+    results = {}
+    for prec in [p for p in args.precisions.split(",") if p]:
+        results[prec] = run_gpu(args, prec, w, golden)
+        _log(f"[bench] {prec}: {results[prec]}")
+    head = results.get("f32") or next(iter(results.values()))
+    d = w.d
+    elem = 8 if head["prec"] == "f32" else 16
+    per_launch = args.batch * 2 * d * d * elem  # read the stage input once, write its output once
+    achieved = per_launch / (head["kern_us"] * 1e-6) / 1e9 if head["kern_us"] > 0 else None
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "grad-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": head["prec"],
+        "data": "synthetic",
+        "config": {
+            "workload": "transmon(3)xresonator(80) d=240, K=4, J=3, N_t=10000, dt=0.002/kappa, smooth-noise controls",
+            "batch": args.batch, "n_t": args.n_t, "path": head["path"], "gradient": args.gmode,
+            "ckpt_stride": int(math.ceil(math.sqrt(args.n_t))), "parallelism": "none (1 GPU)",
+        },
+        "rk_steps_per_s": head["value"] * args.n_t * 3,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "band_stage_kernel" if head["path"] == "banded" else "zgemm_kernel",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": measured_traffic(head["prec"], args.batch, head["path"]),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000)",
+            "kernel_avg_us": head["kern_us"],
+            "kernel_samples": head["kern_n"],
+            "algorithmic_bytes_per_launch": per_launch,
+        },
+    }
+    if "err_phi" in head:
+        line["err_vs_oracle"] = {"phi": head["err_phi"], "grad": head["err_grad"], "problem": 0}
+    if "f64" in results and "f32" in results:
+        f64 = results["f64"]
+        line["fp64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
+                        "err_vs_oracle": {"phi": f64.get("err_phi"), "grad": f64.get("err_grad")}}
+        line["speedup_fp32_over_fp64"] = head["value"] / f64["value"]
+    if not args.no_cpu_baseline:
+        _log("[bench] cpu baseline (oracle sample)")
+        line["cpu_baseline"] = cpu_baseline(args, w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -173,6 +173,18 @@ og_status og_adjoint(og_ctx *ctx, const void *sigma, void *stream);
  */
 og_status og_gradient(og_ctx *ctx, double *grad, void *stream);
 
+/*
+ * Kernel timing (tracing aid, off by default).  With every > 0, one launch in
+ * `every` of the context's right-hand-side kernel (the banded stencil stage
+ * kernel, or on the dense path the first GEMM of each stage) is bracketed by
+ * a pair of HIP events on the stream it is launched on; at most 65536
+ * launches are sampled.  every = 0 stops sampling.  og_profile_read waits
+ * for the sampled events, returns the mean device duration in microseconds
+ * and the number of samples, and clears the samples.
+ */
+og_status og_profile(og_ctx *ctx, int every);
+og_status og_profile_read(og_ctx *ctx, double *mean_us, long *count);
+
 /* Static text for a status code. */
 const char *og_status_string(og_status s);
 

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libopengrape.so")
+LIB_PATH = os.environ.get("OPENGRAPE_LIB") or os.path.join(_HERE, "libopengrape.so")
 
 PREC = {"f64": 0, "f32": 1}
 GMODE = {"grape1": 0, "exact": 1}
@@ -36,7 +36,8 @@ STATUS = {
 # Every symbol declared in include/opengrape.h.
 EXPORTS = (
     "og_default_options", "og_create", "og_destroy", "og_path_used", "og_workspace_bytes",
-    "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_status_string", "og_last_error",
+    "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_profile", "og_profile_read",
+    "og_status_string", "og_last_error",
 )
 
 
@@ -82,6 +83,10 @@ def load_library(path: str = LIB_PATH):
     lib.og_adjoint.restype = i
     lib.og_gradient.argtypes = [vp, vp, vp]
     lib.og_gradient.restype = i
+    lib.og_profile.argtypes = [vp, i]
+    lib.og_profile.restype = i
+    lib.og_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
+    lib.og_profile_read.restype = i
     lib.og_status_string.argtypes = [i]
     lib.og_status_string.restype = ctypes.c_char_p
     lib.og_last_error.argtypes = []
@@ -226,6 +231,18 @@ class Problem:
         with torch.cuda.device(self.device):
             _check(self._lib.og_gradient(self._ctx, g.data_ptr(), _stream_ptr(self.device)))
         return g
+
+    def profile(self, every: int):
+        """Sample one right-hand-side kernel launch in `every` with HIP events (0 = off)."""
+        _check(self._lib.og_profile(self._ctx, int(every)))
+
+    def profile_read(self):
+        """(mean device duration in microseconds, number of samples) of the sampled launches."""
+        mean = ctypes.c_double()
+        cnt = ctypes.c_long()
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_profile_read(self._ctx, ctypes.byref(mean), ctypes.byref(cnt)))
+        return mean.value, cnt.value
 
     def cost_and_grad(self, u, rho0, sigma, dt, workspace=None):
         """Phi[b] and dPhi/du[b] for a batch of control arrays."""

@@ -211,6 +211,33 @@ struct og_ctx {
   double h0_frob = 0, diss_bound = 0;
   int* status_dev = nullptr;
   double* umax_dev = nullptr;
+  // kernel timing samples (og_profile)
+  int prof_every = 0;
+  long prof_counter = 0;
+  std::vector<hipEvent_t> prof_ev;  // start, stop pairs
+  size_t prof_used = 0;             // pairs recorded
+
+  // Record the start event of a sampled launch; returns the pair index or -1.
+  long prof_begin(hipStream_t st) {
+    if (prof_every <= 0) return -1;
+    if ((prof_counter++ % prof_every) != 0) return -1;
+    if (prof_used >= 65536) return -1;
+    if (prof_ev.size() < 2 * (prof_used + 1)) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return -1;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return -1;
+      }
+      prof_ev.push_back(a);
+      prof_ev.push_back(b);
+    }
+    if (hipEventRecord(prof_ev[2 * prof_used], st) != hipSuccess) return -1;
+    return (long)prof_used++;
+  }
+  void prof_end(long idx, hipStream_t st) {
+    if (idx >= 0) (void)hipEventRecord(prof_ev[2 * idx + 1], st);
+  }
 };
 
 namespace {
@@ -254,6 +281,7 @@ struct Engine : EngineBase {
   og::cpx<T>*Z1, *Z2, *Z3, *Zb1, *Zb2, *Zb3;
   og::cpx<T>*st_hi, *st_lo;  // substep start states (EXACT, n_sub > 1)
   og::cpx<T>*Aj[2], *X, *W, *Wp;
+  og::cpx<T>* acoef[2];  // banded: per-slice diagonal coefficients, per direction
   double* grad;
 
   Engine(og_ctx* c) : ctx(c), d(c->d), K(c->K), J(c->J), banded(c->path == OG_PATH_BANDED), E((long)c->d * c->d) {}
@@ -353,7 +381,7 @@ struct Engine : EngineBase {
   };
   enum {
     L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
-    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_GRAD, L_N
+    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_COEF, L_GRAD, L_N
   };
 
   int stride_for(int nt) const {
@@ -392,8 +420,11 @@ struct Engine : EngineBase {
       sz[L_X] = m;
       sz[L_W] = (size_t)std::max(J, 1) * m;
       sz[L_WP] = (exact ? 4 : 1) * m;
+    } else {
+      sz[L_COEF] = 2 * (size_t)b * og::MAXA * d * sizeof(og::cpx<T>);
     }
-    sz[L_GRAD] = (size_t)b * nt * std::max(K, 1) * sizeof(double);
+    // per-slice gradient partial sums, one per row chunk of the contraction
+    sz[L_GRAD] = (size_t)b * nt * og::NCH * std::max(K, 1) * sizeof(double);
     size_t pos = 0;
     for (int i = 0; i < L_N; ++i) {
       L.off[i] = pos;
@@ -420,6 +451,25 @@ struct Engine : EngineBase {
     return io;
   }
 
+  // The stage kernel is compiled for a few upper bounds of the number of
+  // diagonals (NA) and dissipator taps (ND); pick the smallest that fits.
+  // Instantiations bounded by 8 diagonals / 4 taps (resonator, transmon x
+  // resonator) or by the library maxima.  Exact-count instantiations were
+  // measured slower: they hoist every tap load of the four rows of a thread
+  // and fall to two waves per SIMD.
+  template <int MODE, int NA, int ND, bool EXACT>
+  void launch_band_v(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
+    og::band_stage_kernel<T, MODE, NA, ND, EXACT><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, coef);
+  }
+  template <int MODE>
+  void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
+    const int na = ops.nA, nd = ops.nD;
+    if (na <= 8 && nd <= 4)
+      launch_band_v<MODE, 8, 4, false>(ops, io, coef);
+    else
+      launch_band_v<MODE, og::MAXA, og::MAXD, false>(ops, io, coef);
+  }
+
   // One Runge-Kutta stage for the whole batch: out = f(L_dir(in)).
   og_status stage(int dr, int mode, int jslice, const og::cpx<T>* in, const og::cpx<T>* shi,
                   const og::cpx<T>* slo, og::cpx<T>* ohi, og::cpx<T>* olo, T coef,
@@ -436,16 +486,17 @@ struct Engine : EngineBase {
     io.ex[1] = ex1;
     io.ex[2] = ex2;
     io.nex = ex2 ? 3 : (ex1 ? 2 : (ex0 ? 1 : 0));
-    const long u_bs = (long)n_t * K;
     if (banded) {
       const og::BandOps<T>& ops = dir[dr].band;
+      const long pidx = ctx->prof_begin(st);
       if (mode == og::SM_STAGE)
-        og::band_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, K, u, u_bs, jslice);
+        launch_band<og::SM_STAGE>(ops, io, acoef[dr]);
       else if (mode == og::SM_FINAL)
-        og::band_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, K, u, u_bs, jslice);
+        launch_band<og::SM_FINAL>(ops, io, acoef[dr]);
       else
-        og::band_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, K, u, u_bs, jslice);
+        launch_band<og::SM_SCALE>(ops, io, acoef[dr]);
       OG_CHECK_LAUNCH();
+      ctx->prof_end(pidx, st);
       return OG_OK;
     }
     // dense: X = A_j in + 1/2 sum gamma C (C in)^dag ... via two GEMMs, then X + X^dag
@@ -477,8 +528,10 @@ struct Engine : EngineBase {
       g.ldb[m] = d;
     }
     const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * g.nm));
+    const long pidx = ctx->prof_begin(st);
     og::zgemm_kernel<T><<<gg, 256, 0, st>>>(g);
     OG_CHECK_LAUNCH();
+    ctx->prof_end(pidx, st);
     if (J > 0) {
       og::GemmArgs<T> h{};
       h.nm = 1;
@@ -510,9 +563,17 @@ struct Engine : EngineBase {
     return OG_OK;
   }
 
+  // Slice generator assembly A(u_j) (Eq. (1)) for direction dr: diagonal
+  // coefficients (banded) or the dense matrix, for every problem.
   og_status assemble(int dr, int jslice) {
-    if (banded) return OG_OK;
     const DirDev<T>& dv = dir[dr];
+    if (banded) {
+      const int n = dv.band.nA * d;
+      const unsigned gx = (unsigned)std::max(1, std::min((n + 255) / 256, 64));
+      og::band_coef_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(dv.band, d, K, u, (long)n_t * K, jslice, acoef[dr]);
+      OG_CHECK_LAUNCH();
+      return OG_OK;
+    }
     const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
     og::assemble_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(dv.A0, dv.Ak, K, E, u, (long)n_t * K, jslice, Aj[dr]);
     OG_CHECK_LAUNCH();
@@ -540,7 +601,7 @@ struct Engine : EngineBase {
   og_status contract(int jslice, int np, const og::cpx<T>* const* Xs, const og::cpx<T>* const* Ls,
                      const double* coefs, int accumulate) {
     if (K == 0) return OG_OK;
-    const long g_bs = (long)n_t * K;
+    const dim3 cg((unsigned)og::NCH, (unsigned)B);
     if (banded) {
       og::PairArgs<T> pa{};
       pa.np = np;
@@ -551,7 +612,12 @@ struct Engine : EngineBase {
         pa.L[p] = Ls[p];
         pa.coef[p] = coefs[p];
       }
-      og::band_contract_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(pa, hband, K, d, grad, g_bs, jslice, accumulate);
+      if (hband.nH <= 4)
+        og::band_contract_kernel<T, 4><<<cg, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
+      else if (hband.nH <= 8)
+        og::band_contract_kernel<T, 8><<<cg, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
+      else
+        og::band_contract_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
       OG_CHECK_LAUNCH();
       return OG_OK;
     }
@@ -576,8 +642,8 @@ struct Engine : EngineBase {
     OG_CHECK_LAUNCH();
     double c[4] = {0, 0, 0, 0};
     for (int p = 0; p < np; ++p) c[p] = coefs[p];
-    og::dense_contract_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(Wp, E, (long)np * E, np, c[0], c[1], c[2], c[3],
-                                                                   HT, K, E, grad, g_bs, jslice, accumulate);
+    og::dense_contract_kernel<T><<<cg, 256, 0, st>>>(Wp, E, (long)np * E, np, c[0], c[1], c[2], c[3], HT, K, E,
+                                                    grad, n_t, jslice, accumulate);
     OG_CHECK_LAUNCH();
     return OG_OK;
   }
@@ -614,6 +680,8 @@ struct Engine : EngineBase {
     X = opt_at(L_X, !banded);
     W = opt_at(L_W, !banded);
     Wp = opt_at(L_WP, !banded);
+    acoef[0] = opt_at(L_COEF, banded);
+    acoef[1] = banded ? acoef[0] + (size_t)b * og::MAXA * d : nullptr;
     grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);
     return OG_OK;
   }
@@ -719,7 +787,10 @@ struct Engine : EngineBase {
   }
 
   og_status gradient(double* out, hipStream_t s) override {
-    OG_HIP(hipMemcpyAsync(out, grad, (size_t)B * n_t * K * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (K == 0) return OG_OK;
+    const long n = (long)B * n_t * K;
+    og::reduce_partials_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(grad, (long)B * n_t, K, out);
+    OG_CHECK_LAUNCH();
     return OG_OK;
   }
 };
@@ -915,6 +986,7 @@ og_status og_destroy(og_ctx* ctx) {
   if (!ctx) return OG_OK;
   (void)hipDeviceSynchronize();
   delete ctx->eng;
+  for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   if (ctx->status_dev) (void)hipFree(ctx->status_dev);
   if (ctx->umax_dev) (void)hipFree(ctx->umax_dev);
   delete ctx;
@@ -1005,6 +1077,34 @@ og_status og_gradient(og_ctx* ctx, double* grad, void* stream) {
     OG_HIP(hipStreamSynchronize(st));
     if (flag) return fail(OG_ERR_NONFINITE, "a propagated state became non-finite");
   }
+  return OG_OK;
+}
+
+og_status og_profile(og_ctx* ctx, int every) {
+  g_err.clear();
+  if (!ctx) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (every < 0) return fail(OG_ERR_ARG, "every must be >= 0");
+  ctx->prof_every = every;
+  ctx->prof_counter = 0;
+  return OG_OK;
+}
+
+og_status og_profile_read(og_ctx* ctx, double* mean_us, long* count) {
+  g_err.clear();
+  if (!ctx || !mean_us || !count) return fail(OG_ERR_ARG, "NULL argument");
+  double total = 0;
+  long n = 0;
+  for (size_t i = 0; i < ctx->prof_used; ++i) {
+    OG_HIP(hipEventSynchronize(ctx->prof_ev[2 * i + 1]));
+    float ms = 0;
+    OG_HIP(hipEventElapsedTime(&ms, ctx->prof_ev[2 * i], ctx->prof_ev[2 * i + 1]));
+    total += ms;
+    ++n;
+  }
+  *mean_us = n ? 1000.0 * total / n : 0.0;
+  *count = n;
+  ctx->prof_used = 0;
+  ctx->prof_counter = 0;
   return OG_OK;
 }
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ int xcd_logical_block(int id, int n) {
 // Runge-Kutta stage input / output description
 // ---------------------------------------------------------------------------
 enum StageMode : int {
-  SM_STAGE = 0,  // out = s_hi + (s_lo + coef * L(in))          Horner stage
+  SM_STAGE = 0,  // out = s_hi + coef * L(in)                   nested RK4 stage
   SM_FINAL = 1,  // (o_hi, o_lo) = (s_hi, s_lo) + coef * L(in) + sum(extra)
                  //                 with a compensated (two-sum) update
   SM_SCALE = 2   // out = coef * L(in)                          adjoint chain
@@ -172,9 +172,10 @@ __device__ __forceinline__ void stage_epilogue(const StageIO<T>& io, int d, int 
       if (MODE == SM_SCALE) {
         oh[q] = cscale(io.coef, val[q]);
       } else if (MODE == SM_STAGE) {
-        cpx<T> h = io.shi[(long)b * io.s_s + e];
-        cpx<T> l = io.slo ? io.slo[(long)b * io.s_s + e] : mkc<T>(0, 0);
-        oh[q] = mkc<T>(h.re + (l.re + io.coef * val[q].re), h.im + (l.im + io.coef * val[q].im));
+        // the stage input is rounded to T anyway: the compensation term of
+        // the state changes it by at most one ulp and is not read here
+        const cpx<T> h = io.shi[(long)b * io.s_s + e];
+        oh[q] = mkc<T>(h.re + io.coef * val[q].re, h.im + io.coef * val[q].im);
       } else {  // SM_FINAL
         cpx<T> dl = cscale(io.coef, val[q]);
         for (int x = 0; x < io.nex; ++x) dl = cadd(dl, io.ex[x][(long)b * io.ex_s + e]);
@@ -208,67 +209,119 @@ __device__ __forceinline__ void stage_epilogue(const StageIO<T>& io, int d, int 
 // i.e. A Y + Y A^dag + sum_m gamma_m C_m Y C_m^dag in diagonal storage.
 // grid.x = B * ntile (upper-triangular tiles), block = 256 threads, each
 // thread owns rows ty, ty+8, ty+16, ty+24 and column tx of the tile.
+// NA / ND bound the number of diagonals / dissipator taps at compile time so
+// that every tap load of an element is issued before the arithmetic; rows
+// and columns outside the matrix are clamped, which is exact because the
+// diagonal-storage coefficient of such a tap is zero.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+__device__ __forceinline__ int clampi(int x, int hi) { return x < 0 ? 0 : (x > hi ? hi : x); }
+
+// Element idx (32-bit, d*d*sizeof < 2^32) of a matrix whose base pointer is
+// wave-uniform, so that the load uses a scalar base and a 32-bit offset.
+template <typename T>
+__device__ __forceinline__ cpx<T> ldm(const cpx<T>* __restrict__ base, unsigned idx) {
+  return *reinterpret_cast<const cpx<T>*>(reinterpret_cast<const char*>(base) +
+                                          (size_t)(idx * (unsigned)sizeof(cpx<T>)));
+}
+
+// Diagonal coefficients of A(u_j) = A0 + sum_k u[b, j, k] Ak for every
+// problem of the batch, once per slice: coef[b][a][i] = A(u_j)[i, i + o_a].
+template <typename T>
+__global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, int K,
+                                                        const double* __restrict__ u, long u_bs, int jslice,
+                                                        cpx<T>* __restrict__ coef) {
+  const int b = blockIdx.y;
+  const double* ub = u + (long)b * u_bs + (long)jslice * K;
+  const int n = ops.nA * d;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    cpx<T> v = ops.A0[e];
+    for (int k = 0; k < K; ++k) {
+      const T uk = (T)ub[k];
+      const cpx<T> h = ops.Ak[(long)k * n + e];
+      v.re += uk * h.re;
+      v.im += uk * h.im;
+    }
+    coef[(long)b * n + e] = v;
+  }
+}
+
+// EXACT: the operator set has exactly NA diagonals and ND taps (no
+// predication); otherwise NA / ND are upper bounds of ops.nA / ops.nD.
+template <typename T, int MODE, int NA, int ND, bool EXACT>
 __global__ __launch_bounds__(256) void band_stage_kernel(BandOps<T> ops, StageIO<T> io,
                                                          const int2* __restrict__ tiles, int ntile, int d,
-                                                         int K, const double* __restrict__ u, long u_bs,
-                                                         int jslice) {
-  __shared__ cpx<T> cR[MAXA][TS];
-  __shared__ cpx<T> cC[MAXA][TS];
+                                                         const cpx<T>* __restrict__ coef) {
+  __shared__ cpx<T> cR[NA][TS];
+  __shared__ cpx<T> cC[NA][TS];
+  __shared__ cpx<T> dR[ND][TS];
+  __shared__ cpx<T> dC[ND][TS];
   __shared__ cpx<T> tile[TS][TS + 1];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   const int2 tt = tiles[t];
   const int I0 = tt.x * TS, J0 = tt.y * TS;
-  const double* ub = u + (long)b * u_bs + (long)jslice * K;
-  const int nA = ops.nA;
-  for (int e = tid; e < 2 * nA * TS; e += 256) {
-    const int side = e / (nA * TS);
-    const int rem = e - side * nA * TS;
-    const int a = rem / TS, r = rem - a * TS;
+  const int nA = EXACT ? NA : ops.nA, nD = EXACT ? ND : ops.nD;
+  const cpx<T>* __restrict__ cb = coef + (long)b * nA * d;
+  for (int e = tid; e < 2 * (nA + nD) * TS; e += 256) {
+    const int side = e / ((nA + nD) * TS);
+    const int rem = e - side * (nA + nD) * TS;
+    const int s = rem / TS, r = rem - s * TS;
     const int idx = (side ? J0 : I0) + r;
     cpx<T> v = mkc<T>(0, 0);
     if (idx < d) {
-      v = ops.A0[(long)a * d + idx];
-      for (int k = 0; k < K; ++k) {
-        const T uk = (T)ub[k];
-        const cpx<T> h = ops.Ak[((long)k * nA + a) * d + idx];
-        v.re += uk * h.re;
-        v.im += uk * h.im;
-      }
+      if (s < nA)
+        v = cb[s * d + idx];
+      else
+        v = side ? ops.Dr[(s - nA) * d + idx] : ops.Dl[(s - nA) * d + idx];
     }
-    if (side)
-      cC[a][r] = v;
-    else
-      cR[a][r] = v;
+    if (s < nA) {
+      if (side)
+        cC[s][r] = v;
+      else
+        cR[s][r] = v;
+    } else {
+      if (side)
+        dC[s - nA][r] = v;
+      else
+        dR[s - nA][r] = v;
+    }
   }
   __syncthreads();
   const cpx<T>* __restrict__ Y = io.in + (long)b * io.in_s;
+  const int dm = d - 1;
+  const int jc = min(J0 + tx, dm);
+  int colA[NA], colD[ND];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) colA[a] = clampi(jc + ops.offA[a], dm);
+#pragma unroll
+  for (int s = 0; s < ND; ++s) colD[s] = clampi(jc + ops.dq[s], dm);
   cpx<T> val[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = ty + 8 * q;
-    const int i = I0 + r, j = J0 + tx;
+    const int ic = min(I0 + r, dm);
+    const unsigned rowi = __umul24(ic, d);
+    cpx<T> yr[NA], yc[NA], yd[ND];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+      if (EXACT || a < nA) {
+        yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
+        yc[a] = ldm(Y, rowi + colA[a]);
+      }
+#pragma unroll
+    for (int s = 0; s < ND; ++s)
+      if (EXACT || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
     cpx<T> acc = mkc<T>(0, 0);
-    if (i < d && j < d) {
-      for (int a = 0; a < nA; ++a) {
-        const int ii = i + ops.offA[a];
-        if ((unsigned)ii < (unsigned)d) cfma(acc, cR[a][r], Y[(long)ii * d + j]);
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+      if (EXACT || a < nA) {
+        cfma(acc, cR[a][r], yr[a]);
+        cfmac(acc, yc[a], cC[a][tx]);
       }
-      for (int a = 0; a < nA; ++a) {
-        const int jj = j + ops.offA[a];
-        if ((unsigned)jj < (unsigned)d) cfmac(acc, Y[(long)i * d + jj], cC[a][tx]);
-      }
-      for (int s = 0; s < ops.nD; ++s) {
-        const int ii = i + ops.dp[s], jj = j + ops.dq[s];
-        if ((unsigned)ii < (unsigned)d && (unsigned)jj < (unsigned)d) {
-          const cpx<T> w = cmulc(ops.Dl[(long)s * d + i], ops.Dr[(long)s * d + j]);
-          cfma(acc, w, Y[(long)ii * d + jj]);
-        }
-      }
-    }
+#pragma unroll
+    for (int s = 0; s < ND; ++s)
+      if (EXACT || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[s]);
     val[q] = acc;
   }
   stage_epilogue<T, MODE>(io, d, b, I0, J0, val, tile, tx, ty);
@@ -505,8 +558,16 @@ __global__ __launch_bounds__(256) void cost_kernel(const double* __restrict__ si
 
 // Gradient contraction, diagonal storage of the H_k:
 //   g[b, j, k] = sum_p coef_p * 2 Im Tr(H_k X_p L_p)
-//   Tr(H X L) = sum_t sum_a H[a, a + o_t] R_t[a],  R_t[a] = sum_c X[a + o_t, c] conj(L[a, c])
-// (L Hermitian).  Each wave computes whole row products R_t[a].
+//   Tr(H X L) = sum_a sum_t H[a, a + o_t] sum_c X[a + o_t, c] conj(L[a, c])
+// (L Hermitian).  The weight H[a, a + o_t] depends on the row only, so every
+// lane multiplies its own column products by it and the lanes are reduced
+// once at the end.  grid = (NCH row chunks, B); every block writes the
+// float64 partial sums of its chunk to part[b][j][chunk][k], which
+// reduce_partials_kernel sums in a fixed order.  Products are formed in T;
+// each lane sums at most ceil(d / 64) * nH of them in T before adding to a
+// float64 accumulator.
+constexpr int NCH = 4;
+
 template <typename T>
 struct PairArgs {
   const cpx<T>* X[MAXP];
@@ -523,13 +584,30 @@ struct HBand {
   const cpx<T>* Hd;  // [K][nH][d]
 };
 
-template <typename T>
+__device__ __forceinline__ void write_partials(double (*sh)[MAXK], const double* acc, int K, double* part,
+                                               long base, int accumulate) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = 0; k < K; ++k) {
+    const double v = wave_sum(acc[k]);
+    if (lane == 0) sh[wave][k] = v;
+  }
+  __syncthreads();
+  if (tid < K) {
+    const double v = ((sh[0][tid] + sh[1][tid]) + sh[2][tid]) + sh[3][tid];
+    double* o = part + base + tid;
+    *o = accumulate ? *o + 2.0 * v : 2.0 * v;
+  }
+}
+
+template <typename T, int NH>
 __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBand<T> hb, int K, int d,
-                                                            double* __restrict__ g, long g_bs, int jslice,
+                                                            double* __restrict__ part, long n_t, int jslice,
                                                             int accumulate) {
   __shared__ double sh[4][MAXK];
-  const int b = blockIdx.x;
+  const int ch = blockIdx.x, b = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int a0 = (int)((long)d * ch / NCH), a1 = (int)((long)d * (ch + 1) / NCH);
+  const int nH = hb.nH, dm = d - 1;
   double acc[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
@@ -537,65 +615,79 @@ __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBan
     const cpx<T>* __restrict__ X = pa.X[p] + (long)b * pa.x_s;
     const cpx<T>* __restrict__ Lm = pa.L[p] + (long)b * pa.l_s;
     const double cf = pa.coef[p];
-    for (int w = wave; w < hb.nH * d; w += 4) {
-      const int t = w / d, a = w - t * d;
-      const int row = a + hb.offH[t];
-      if ((unsigned)row >= (unsigned)d) continue;
-      double rr = 0.0, ri = 0.0;
-      for (int c = lane; c < d; c += 64) {
-        const cpx<T> x = X[(long)row * d + c];
-        const cpx<T> l = Lm[(long)a * d + c];
-        rr += (double)(x.re * l.re + x.im * l.im);
-        ri += (double)(x.im * l.re - x.re * l.im);
+    for (int a = a0 + wave; a < a1; a += 4) {
+      // this lane's part of the row products P_t = sum_c X[a + o_t, c] conj(L[a, c])
+      cpx<T> P[NH];
+#pragma unroll
+      for (int t = 0; t < NH; ++t) P[t] = mkc<T>(0, 0);
+      for (int c0 = 0; c0 < d; c0 += 64) {
+        const int c = c0 + lane;
+        const int cc = min(c, dm);
+        cpx<T> l = ldm(Lm, __umul24(a, d) + cc);
+        if (c > dm) l = mkc<T>(0, 0);
+        cpx<T> x[NH];
+#pragma unroll
+        for (int t = 0; t < NH; ++t)
+          if (t < nH) x[t] = ldm(X, __umul24(clampi(a + hb.offH[t], dm), d) + cc);
+#pragma unroll
+        for (int t = 0; t < NH; ++t)
+          if (t < nH) cfmac(P[t], x[t], l);
       }
-      rr = wave_sum(rr);
-      ri = wave_sum(ri);
+      // weight by H_k[a, a + o_t] once per row
       for (int k = 0; k < K; ++k) {
-        const cpx<T> h = hb.Hd[((long)k * hb.nH + t) * d + a];
-        acc[k] += cf * ((double)h.re * ri + (double)h.im * rr);
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < NH; ++t)
+          if (t < nH) {
+            const cpx<T> h = hb.Hd[((long)k * nH + t) * d + a];
+            s += (double)h.re * (double)P[t].im + (double)h.im * (double)P[t].re;
+          }
+        acc[k] += cf * s;
       }
     }
   }
-  if (lane == 0)
-    for (int k = 0; k < K; ++k) sh[wave][k] = acc[k];
-  __syncthreads();
-  if (tid < K) {
-    const double s = ((sh[0][tid] + sh[1][tid]) + sh[2][tid]) + sh[3][tid];
-    double* o = g + (long)b * g_bs + (long)jslice * K + tid;
-    *o = accumulate ? *o + 2.0 * s : 2.0 * s;
-  }
+  write_partials(sh, acc, K, part, (((long)b * n_t + jslice) * NCH + ch) * K, accumulate);
 }
 
-// Dense contraction: W_p = X_p L_p already formed; Tr(H_k W) = sum_e HT_k[e] W[e]
-// with HT_k the transpose of H_k.  g = sum_p coef_p 2 Im Tr(H_k W_p).
+// Dense contraction: W_p = X_p L_p already formed by the GEMM; with HT_k the
+// transpose of H_k, Tr(H_k W) = sum_e HT_k[e] W[e].  grid = (NCH, B).
 template <typename T>
 __global__ __launch_bounds__(256) void dense_contract_kernel(const cpx<T>* __restrict__ W, long w_s_p,
                                                              long w_s_b, int np, double c0, double c1,
                                                              double c2, double c3,
                                                              const cpx<T>* __restrict__ HT, int K, long n,
-                                                             double* __restrict__ g, long g_bs, int jslice,
+                                                             double* __restrict__ part, long n_t, int jslice,
                                                              int accumulate) {
-  __shared__ double sh[256];
-  const int b = blockIdx.x;
+  __shared__ double sh[4][MAXK];
+  const int ch = blockIdx.x, b = blockIdx.y;
+  const long e0 = n * ch / NCH, e1 = n * (ch + 1) / NCH;
   const double cf[4] = {c0, c1, c2, c3};
-  for (int k = 0; k < K; ++k) {
-    double acc = 0.0;
-    for (int p = 0; p < np; ++p) {
-      const cpx<T>* __restrict__ Wp = W + (long)b * w_s_b + (long)p * w_s_p;
-      double part = 0.0;
-      for (long e = threadIdx.x; e < n; e += 256) {
+  double acc[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
+  for (int p = 0; p < np; ++p) {
+    const cpx<T>* __restrict__ Wp = W + (long)b * w_s_b + (long)p * w_s_p;
+    for (long e = e0 + threadIdx.x; e < e1; e += 256) {
+      const cpx<T> w = Wp[e];
+      for (int k = 0; k < K; ++k) {
         const cpx<T> h = HT[(long)k * n + e];
-        const cpx<T> w = Wp[e];
-        part += (double)(h.re * w.im + h.im * w.re);
+        acc[k] += cf[p] * (double)(h.re * w.im + h.im * w.re);
       }
-      acc += cf[p] * part;
-    }
-    const double s = block_sum256(acc, sh);
-    if (threadIdx.x == 0) {
-      double* o = g + (long)b * g_bs + (long)jslice * K + k;
-      *o = accumulate ? *o + 2.0 * s : 2.0 * s;
     }
   }
+  write_partials(sh, acc, K, part, (((long)b * n_t + jslice) * NCH + ch) * K, accumulate);
+}
+
+// grad[b, j, k] = sum_ch part[b, j, ch, k] in chunk order.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __restrict__ part, long n_bj, int K,
+                                                              double* __restrict__ grad) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_bj * K) return;
+  const long bj = idx / K;
+  const int k = (int)(idx - bj * K);
+  double s = 0.0;
+  for (int ch = 0; ch < NCH; ++ch) s += part[(bj * NCH + ch) * K + k];
+  grad[idx] = s;
 }
 
 // ---------------------------------------------------------------------------

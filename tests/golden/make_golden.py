@@ -1,0 +1,65 @@
+"""Write the stored expected values used by the full-size GPU parity tests.
+
+Every number here comes from the float64 oracle (oracle/) on the seeded
+workloads (workloads/); nothing is read from the GPU library.  Run from the
+repository root:  python tests/golden/make_golden.py [c2] [c3] [c4]
+(all three when no argument is given).  The C3 case needs about 10 GB of
+memory and tens of minutes on 8 cores.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+from oracle import rk  # noqa: E402
+
+
+def _run(w, u, sparse, exact=True):
+    m = rk.Model.from_workload(w, sparse=sparse)
+    t0 = time.time()
+    rhos = rk.forward(m, u, w.rho0, w.dt)
+    phi = rk.cost(w.sigma, rhos[-1])
+    lams = rk.backward(m, u, w.sigma, w.dt)
+    g1 = rk.gradient_grape1(m, u, rhos, lams, w.dt)
+    del lams
+    ge = None
+    if exact:
+        ge, _ = rk.gradient_exact(m, u, rhos, w.sigma, w.dt)
+    rhoT = rhos[-1]
+    print(f"{w.name}: Phi = {phi:.15g}  ({time.time() - t0:.0f} s)", flush=True)
+    return phi, g1, ge, rhoT
+
+
+def c2():
+    w = wl.config_c2()
+    phi, g1, ge, rhoT = _run(w, w.u, sparse=False)
+    np.savez_compressed(os.path.join(HERE, "c2_cqed_d90.npz"), phi=phi, g_grape1=g1, g_exact=ge, rhoT=rhoT)
+
+
+def c3():
+    w = wl.config_c3(batch=1)
+    phi, g1, ge, rhoT = _run(w, w.u, sparse=True)
+    np.savez_compressed(os.path.join(HERE, "c3_cqed_d240.npz"), phi=phi, g_grape1=g1, g_exact=ge,
+                        rhoT_diag=np.diag(rhoT).real.copy(), rhoT_rows=rhoT[[0, 80, 81, 161, 239]].copy())
+
+
+def c4(n_t=100):
+    w = wl.config_c4()
+    u = w.u[:n_t]
+    phi, g1, ge, rhoT = _run(w, u, sparse=False, exact=False)
+    np.savez_compressed(os.path.join(HERE, f"c4_dense_d512_nt{n_t}.npz"), phi=phi, g_grape1=g1,
+                        rhoT_rows=rhoT[[0, 255, 511]].copy(), rhoT_diag=np.diag(rhoT).real.copy())
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["c2", "c3", "c4"]
+    for name in which:
+        {"c2": c2, "c3": c3, "c4": c4}[name]()
