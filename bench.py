@@ -46,7 +46,47 @@ def _parse():
     ap.add_argument("--profile-every", type=int, default=97)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes 5 times (for scaling HBM counters)")
+    ap.add_argument("--serve-requests", type=int, default=384,
+                    help="requests of the serving leg at the offered load (0 = no serving leg)")
+    ap.add_argument("--serve-saturation", type=int, default=192,
+                    help="requests submitted at once to measure the saturation throughput")
+    ap.add_argument("--serve-loads", default="0.8", help="offered loads as fractions of saturation")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-only", action="store_true")
     return ap.parse_args()
+
+
+def serving_leg(args):
+    """Continuous batching of forward + gradient requests of mixed shape
+    (transmon(n_q) x resonator(N), d in {20, 40, 90, 160, 240}) and length
+    (N_t in [500, 5000]), float32, under an HBM budget.  The saturation
+    throughput is measured with all of a first sample submitted at once; the
+    next requests then arrive as a Poisson stream at the offered load."""
+    import workloads as wl
+    from paper_1609_03170_amd.serve import ServingLoop
+
+    n_sat, n_load = args.serve_saturation, args.serve_requests
+    reqs = wl.serving_requests(n_sat + n_load, seed=10, arrival_seed=9, rate=1.0)
+    models = {s: wl.serving_model(s) for s in wl.SERVING_SHAPES}
+    loop = ServingLoop(models, prec="f32", budget_bytes=int(args.serve_budget_gib * 2**30), max_slices=16)
+    _log(f"[serve] saturation run: {n_sat} requests at t=0")
+    sat = loop.run([dict(r, arrival=0.0) for r in reqs[:n_sat]], wl.serving_controls, log=_log)
+    thr = sat.throughput()
+    out = {"saturation_req_per_s": thr, "saturation_requests": n_sat, "budget_gib": args.serve_budget_gib,
+           "workload": "Poisson stream, d in {20,40,90,160,240}, N_t ~ U[500,5000], dt=0.002, float32, "
+                       "first-order gradient", "loads": []}
+    tail = reqs[n_sat:]
+    t_first = tail[0]["arrival"]
+    for load in [float(x) for x in args.serve_loads.split(",") if x]:
+        rate = load * thr
+        _log(f"[serve] offered load {load:.2f} x saturation = {rate:.2f} req/s, {n_load} requests")
+        stream = [dict(r, arrival=r["arrival"] - t_first) for r in tail]
+        res = loop.run(stream, wl.serving_controls, time_scale=1.0 / rate, log=_log)
+        out["loads"].append({"offered_load": load, "offered_req_per_s": rate, "requests": n_load,
+                             "throughput_req_per_s": res.throughput(), "p50_ms": 1000 * res.percentile(50),
+                             "p99_ms": 1000 * res.percentile(99), "peak_hbm_gib": res.peak_bytes / 2**30})
+    loop.close()
+    return out
 
 
 def copy_probe(nbytes):
@@ -173,6 +213,9 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return
     import workloads as wl
 
     _log(f"[bench] generating inputs B={args.batch} N_t={args.n_t}")
@@ -228,6 +271,8 @@ def main():
         line["fp64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                         "err_vs_oracle": {"phi": f64.get("err_phi"), "grad": f64.get("err_grad")}}
         line["speedup_fp32_over_fp64"] = head["value"] / f64["value"]
+    if args.serve_requests > 0:
+        line["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         _log("[bench] cpu baseline (oracle sample)")
         line["cpu_baseline"] = cpu_baseline(args, w)

@@ -174,6 +174,63 @@ og_status og_adjoint(og_ctx *ctx, const void *sigma, void *stream);
 og_status og_gradient(og_ctx *ctx, double *grad, void *stream);
 
 /*
+ * Continuous batching (serving).  A server accepts independent requests
+ * (one control array each, any N_t, on the context's operator set) while
+ * others are in flight, and advances all of them together: every
+ * og_server_step moves each active request by up to max_slices slice
+ * operations (forward slices, then per checkpoint segment the recompute and
+ * the adjoint slices with their first-order gradient, Eq. (13)), launching
+ * one batched kernel per Runge-Kutta stage for all requests at the same
+ * kind of operation.  The result of a request is identical to evaluating it
+ * alone with og_forward / og_cost / og_adjoint / og_gradient (the kernels
+ * and the reduction order are the same).  Banded path only; gradient mode
+ * GRAPE1 (the context's gmode is ignored).  One server per context; the
+ * server borrows the context, which must outlive it.
+ */
+typedef struct og_server og_server;
+
+typedef struct {
+    int n_t;            /* slices, >= 1                                        */
+    double dt;          /* slice length, > 0                                   */
+    const double *u;    /* device, float64 n_t x K                             */
+    const void *rho0;   /* device, complex128 d x d                            */
+    const void *sigma;  /* device, complex128 d x d (Hermitian)                */
+    double *phi;        /* device, 1 float64: Phi (written at completion)      */
+    double *grad;       /* device, float64 n_t x K: dPhi/du (at completion)    */
+    void *ws;           /* device workspace, 256-byte aligned                  */
+    size_t ws_bytes;    /* >= og_workspace_bytes(ctx, 1, n_t)                  */
+    long tag;           /* caller's identifier, reported at completion         */
+} og_request;
+
+/* Create a server for ctx admitting at most max_active requests at a time
+ * (1 <= max_active <= 65536).  The HBM budget is the caller's: every request
+ * brings its own workspace. */
+og_status og_server_create(og_server **out, og_ctx *ctx, int max_active);
+
+/* Admit a request.  Returns OG_ERR_WORKSPACE when max_active requests are
+ * in flight (nothing is enqueued), OG_ERR_ARG / OG_ERR_UNSTABLE_DT for bad
+ * arguments (with validate = 1 the stability check reads max|u| back, one
+ * sync of `stream`).  All pointers must stay valid until the tag is
+ * reported by og_server_completed. */
+og_status og_server_submit(og_server *s, const og_request *req, void *stream);
+
+/* Enqueue up to max_slices slice operations for every active request on
+ * `stream` (asynchronous).  Requests that finish during the call are
+ * retired; their tags become available from og_server_completed and their
+ * results are valid once the enqueued work has completed on the stream. */
+og_status og_server_step(og_server *s, int max_slices, void *stream);
+
+/* Number of requests in flight. */
+int og_server_active(const og_server *s);
+
+/* Move up to max_tags tags of retired requests (oldest first) to tags;
+ * returns how many. */
+int og_server_completed(og_server *s, long *tags, int max_tags);
+
+/* Destroy the server (requests still in flight are dropped). */
+og_status og_server_destroy(og_server *s);
+
+/*
  * Kernel timing (tracing aid, off by default).  With every > 0, one launch in
  * `every` of the context's right-hand-side kernel (the banded stencil stage
  * kernel, or on the dense path the first GEMM of each stage) is bracketed by

@@ -37,8 +37,15 @@ STATUS = {
 EXPORTS = (
     "og_default_options", "og_create", "og_destroy", "og_path_used", "og_workspace_bytes",
     "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_profile", "og_profile_read",
-    "og_status_string", "og_last_error",
+    "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
+    "og_server_destroy", "og_status_string", "og_last_error",
 )
+
+
+class OgRequest(ctypes.Structure):
+    _fields_ = [("n_t", ctypes.c_int), ("dt", ctypes.c_double), ("u", ctypes.c_void_p), ("rho0", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("tag", ctypes.c_long)]
 
 
 class OgOptions(ctypes.Structure):
@@ -87,6 +94,18 @@ def load_library(path: str = LIB_PATH):
     lib.og_profile.restype = i
     lib.og_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
     lib.og_profile_read.restype = i
+    lib.og_server_create.argtypes = [ctypes.POINTER(vp), vp, i]
+    lib.og_server_create.restype = i
+    lib.og_server_submit.argtypes = [vp, ctypes.POINTER(OgRequest), vp]
+    lib.og_server_submit.restype = i
+    lib.og_server_step.argtypes = [vp, i, vp]
+    lib.og_server_step.restype = i
+    lib.og_server_active.argtypes = [vp]
+    lib.og_server_active.restype = i
+    lib.og_server_completed.argtypes = [vp, ctypes.POINTER(ctypes.c_long), i]
+    lib.og_server_completed.restype = i
+    lib.og_server_destroy.argtypes = [vp]
+    lib.og_server_destroy.restype = i
     lib.og_status_string.argtypes = [i]
     lib.og_status_string.restype = ctypes.c_char_p
     lib.og_last_error.argtypes = []
@@ -281,3 +300,78 @@ class OpenGrapeCost(torch.autograd.Function):
 
 def open_grape_cost(u, problem, rho0, sigma, dt):
     return OpenGrapeCost.apply(u, problem, rho0, sigma, dt)
+
+
+class Server:
+    """Continuous-batching front end of og_server_* for one Problem (banded
+    path, first-order gradient).  Each admitted request owns its inputs, its
+    outputs and its workspace (a torch allocation, so the HBM budget is the
+    caller's); they are kept alive here until the request is retired."""
+
+    def __init__(self, problem: Problem, max_active: int = 1024):
+        self.problem = problem
+        self._lib = problem._lib
+        srv = ctypes.c_void_p()
+        _check(self._lib.og_server_create(ctypes.byref(srv), problem._ctx, int(max_active)))
+        self._srv = srv
+        self._live = {}
+        self.max_active = max_active
+
+    def request_bytes(self, n_t: int) -> int:
+        """Device bytes a request of n_t slices holds while in flight."""
+        p = self.problem
+        return p.workspace_bytes(1, n_t) + 8 * (n_t * p.K + 1)
+
+    def submit(self, tag: int, u, rho0, sigma, dt: float):
+        """Admit one request; u [N_t, K] float64, rho0 / sigma [d, d]
+        complex128, all on the problem's device.  Returns False when the
+        server is full."""
+        p = self.problem
+        u = u.contiguous()
+        n_t = u.shape[0]
+        ws_bytes = p.workspace_bytes(1, n_t)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=p.device)
+        phi = torch.empty(1, dtype=torch.float64, device=p.device)
+        grad = torch.empty((n_t, p.K), dtype=torch.float64, device=p.device)
+        req = OgRequest(n_t, float(dt), u.data_ptr(), rho0.data_ptr(), sigma.data_ptr(), phi.data_ptr(),
+                        grad.data_ptr(), ws.data_ptr(), ws_bytes, int(tag))
+        with torch.cuda.device(p.device):
+            st = self._lib.og_server_submit(self._srv, ctypes.byref(req), _stream_ptr(p.device))
+        if st == -5 and b"server full" in self._lib.og_last_error():
+            return False
+        _check(st)
+        self._live[int(tag)] = dict(u=u, rho0=rho0, sigma=sigma, ws=ws, phi=phi, grad=grad, n_t=n_t)
+        return True
+
+    def step(self, max_slices: int = 8):
+        with torch.cuda.device(self.problem.device):
+            _check(self._lib.og_server_step(self._srv, int(max_slices), _stream_ptr(self.problem.device)))
+
+    @property
+    def active(self) -> int:
+        return int(self._lib.og_server_active(self._srv))
+
+    def completed(self):
+        """Retired requests as {tag: (phi tensor, grad tensor)}; valid once the
+        work enqueued on the stream has finished."""
+        out = {}
+        buf = (ctypes.c_long * 256)()
+        while True:
+            n = self._lib.og_server_completed(self._srv, buf, 256)
+            for i in range(n):
+                rec = self._live.pop(int(buf[i]))
+                out[int(buf[i])] = (rec["phi"], rec["grad"])
+            if n < 256:
+                return out
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            self._lib.og_server_destroy(self._srv)
+            self._srv = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -171,6 +171,8 @@ std::vector<cd> concat(const std::vector<std::vector<cd>>& parts) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int kUmaxBlocks = 64;  // blocks of the max|u| reduction
+
 // ---------------------------------------------------------------------------
 // Operator data of one direction of propagation
 //   forward : A = G = -i H - 1/2 sum gamma c^dag c,  C_m = c_m
@@ -198,6 +200,17 @@ struct EngineBase {
   virtual og_status cost(const void* sigma, double* phi, hipStream_t st) = 0;
   virtual og_status adjoint(const void* sigma, hipStream_t st) = 0;
   virtual og_status gradient(double* grad, hipStream_t st) = 0;
+  // continuous batching (og_server_*)
+  virtual og_status serve_submit(const og_request& r, hipStream_t st) = 0;
+  virtual og_status serve_step(int max_slices, hipStream_t st, std::vector<long>& done) = 0;
+  virtual int serve_active() const = 0;
+  virtual void serve_clear() = 0;
+};
+
+struct og_server {
+  og_ctx* ctx = nullptr;
+  int max_active = 0;
+  std::vector<long> completed;
 };
 
 struct og_ctx {
@@ -718,14 +731,14 @@ struct Engine : EngineBase {
     }
     if (rhoT) {
       const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
-      og::store_state_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(cur_hi, cur_lo, E, E, static_cast<double*>(rhoT));
+      og::store_state_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(cur_hi, cur_lo, E, d, static_cast<double*>(rhoT));
       OG_CHECK_LAUNCH();
     }
     return OG_OK;
   }
 
   og_status cost(const void* sigma, double* phi, hipStream_t s) override {
-    og::cost_kernel<T><<<dim3((unsigned)B), 256, 0, s>>>(static_cast<const double*>(sigma), cur_hi, cur_lo, E, E, phi);
+    og::cost_kernel<T><<<dim3((unsigned)B), 256, 0, s>>>(static_cast<const double*>(sigma), cur_hi, cur_lo, E, d, phi);
     OG_CHECK_LAUNCH();
     return OG_OK;
   }
@@ -791,6 +804,262 @@ struct Engine : EngineBase {
     const long n = (long)B * n_t * K;
     og::reduce_partials_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(grad, (long)B * n_t, K, out);
     OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
+  // -------------------------------------------------------------------------
+  // Continuous batching.  Every request runs the same sequence as a batch of
+  // one through forward() / cost() / adjoint() / gradient(): forward slices
+  // with a checkpoint every S slices, the cost, then per segment (last
+  // first) the recompute and the adjoint slices with the first-order
+  // contraction.  Requests at the same kind of slice operation share the
+  // launches of one step.
+  // -------------------------------------------------------------------------
+  enum { PH_FWD = 1, PH_RECOMP = 2, PH_ADJ = 3, PH_DONE = 4 };
+  struct Slot {
+    og_request r;
+    int S = 1, n_seg = 1;
+    og::cpx<T>*cur_hi, *cur_lo, *lam_hi, *lam_lo, *za, *zb, *ck_hi, *ck_lo, *sg_hi, *sg_lo, *coefF, *coefA;
+    double* part;
+    int phase = 0, j = 0, seg = 0, jj = 0, n = 0;
+    bool inited = false;
+    og::cpx<T>* ck(int i) const { return ck_hi + (long)i * ctxE; }
+    og::cpx<T>* ckl(int i) const { return ck_lo ? ck_lo + (long)i * ctxE : nullptr; }
+    og::cpx<T>* sg(int i) const { return sg_hi + (long)i * ctxE; }
+    og::cpx<T>* sgl(int i) const { return sg_lo ? sg_lo + (long)i * ctxE : nullptr; }
+    long ctxE = 0;
+  };
+  std::vector<Slot> slots;
+
+  og_status serve_submit(const og_request& r, hipStream_t s) override {
+    if (!banded) return fail(OG_ERR_SHAPE, "serving needs the banded path");
+    if (r.ws_bytes < ws_bytes(1, r.n_t)) return fail(OG_ERR_WORKSPACE, "request workspace too small");
+    Slot sl;
+    sl.r = r;
+    sl.ctxE = E;
+    sl.S = stride_for(r.n_t);
+    sl.n_seg = (r.n_t + sl.S - 1) / sl.S;
+    const Layout L = layout(1, r.n_t);
+    char* p = static_cast<char*>(r.ws);
+    auto at = [&](int i) { return reinterpret_cast<og::cpx<T>*>(p + L.off[i]); };
+    sl.cur_hi = at(L_CUR_HI);
+    sl.cur_lo = comp ? at(L_CUR_LO) : nullptr;
+    sl.lam_hi = at(L_LAM_HI);
+    sl.lam_lo = comp ? at(L_LAM_LO) : nullptr;
+    sl.za = at(L_ZA);
+    sl.zb = at(L_ZB);
+    sl.ck_hi = at(L_CK_HI);
+    sl.ck_lo = comp ? at(L_CK_LO) : nullptr;
+    sl.sg_hi = at(L_SG_HI);
+    sl.sg_lo = comp ? at(L_SG_LO) : nullptr;
+    sl.coefF = at(L_COEF);
+    sl.coefA = sl.coefF + (size_t)og::MAXA * d;
+    sl.part = reinterpret_cast<double*>(p + L.off[L_GRAD]);
+    (void)s;
+    slots.push_back(sl);
+    return OG_OK;
+  }
+
+  int serve_active() const override { return (int)slots.size(); }
+  void serve_clear() override { slots.clear(); }
+
+  og_status load1(const void* src, long src_s, og::cpx<T>* hi, og::cpx<T>* lo, hipStream_t s) {
+    const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
+    og::load_state_kernel<T><<<dim3(gx, 1), 256, 0, s>>>(static_cast<const double*>(src), src_s, E, hi, lo, E);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+  og_status copy1(og::cpx<T>* dhi, og::cpx<T>* dlo, const og::cpx<T>* shi, const og::cpx<T>* slo, hipStream_t s) {
+    OG_HIP(hipMemcpyAsync(dhi, shi, (size_t)E * sizeof(og::cpx<T>), hipMemcpyDeviceToDevice, s));
+    if (comp) OG_HIP(hipMemcpyAsync(dlo, slo, (size_t)E * sizeof(og::cpx<T>), hipMemcpyDeviceToDevice, s));
+    return OG_OK;
+  }
+  og_status start_segment(Slot& sl, hipStream_t s) {
+    const int j0 = sl.seg * sl.S;
+    sl.n = std::min(sl.r.n_t, j0 + sl.S) - j0;
+    sl.jj = 0;
+    sl.phase = PH_RECOMP;
+    return copy1(sl.sg(0), sl.sgl(0), sl.ck(sl.seg), sl.ckl(sl.seg), s);
+  }
+
+  struct Op {
+    int slot;
+    int slice;
+    const og::cpx<T>*ihi, *ilo;
+    og::cpx<T>*ohi, *olo;
+    const og::cpx<T>* pairX;
+  };
+
+  template <int MODE, int NA, int ND>
+  void launch_slots_v(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
+    og::band_stage_slots_kernel<T, MODE, NA, ND><<<dim3((unsigned)(n * ntile)), 256, 0, st>>>(
+        dir[dr].band, tab, in_role, out_role, coef, ctx->status_dev, tiles, ntile, d);
+  }
+  template <int MODE>
+  og_status launch_slots(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
+    const og::BandOps<T>& ops = dir[dr].band;
+    const long pidx = ctx->prof_begin(st);
+    if (ops.nA <= 8 && ops.nD <= 4)
+      launch_slots_v<MODE, 8, 4>(dr, tab, n, in_role, out_role, coef);
+    else
+      launch_slots_v<MODE, og::MAXA, og::MAXD>(dr, tab, n, in_role, out_role, coef);
+    OG_CHECK_LAUNCH();
+    ctx->prof_end(pidx, st);
+    return OG_OK;
+  }
+
+  // One slice operation (n_sub RK4 steps) for up to MAXSLOT requests of the
+  // same direction and slice length; adjoint operations first contract the
+  // first-order gradient of their slice.
+  og_status run_chunk(int dr, const std::vector<Op>& ops, size_t i0, size_t i1, double dtv) {
+    const int n = (int)(i1 - i0);
+    og::SlotTable<T> tab{};
+    for (int q = 0; q < n; ++q) {
+      const Op& o = ops[i0 + q];
+      const Slot& sl = slots[o.slot];
+      og::SlotEntry<T>& e = tab.e[q];
+      e.s_hi = o.ihi;
+      e.s_lo = o.ilo;
+      e.o_hi = o.ohi;
+      e.o_lo = o.olo;
+      e.za = sl.za;
+      e.zb = sl.zb;
+      e.coef = dr == FWD ? sl.coefF : sl.coefA;
+      e.urow = sl.r.u + (long)o.slice * K;
+    }
+    if (dr == ADJ && K > 0) {
+      og::PairSlots<T> ps{};
+      for (int q = 0; q < n; ++q) {
+        const Op& o = ops[i0 + q];
+        const Slot& sl = slots[o.slot];
+        ps.X[q] = o.pairX;
+        ps.L[q] = sl.lam_hi;
+        ps.out[q] = sl.part + (long)o.slice * og::NCH * K;
+      }
+      const dim3 cg((unsigned)og::NCH, (unsigned)n);
+      if (hband.nH <= 4)
+        og::band_contract_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
+      else if (hband.nH <= 8)
+        og::band_contract_slots_kernel<T, 8><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
+      else
+        og::band_contract_slots_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
+      OG_CHECK_LAUNCH();
+    }
+    const int na = dir[dr].band.nA * d;
+    const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
+    og::band_coef_slots_kernel<T><<<dim3(gx, (unsigned)n), 256, 0, st>>>(dir[dr].band, tab, d, K);
+    OG_CHECK_LAUNCH();
+    const int nsub = ctx->opt.n_sub;
+    const T h = (T)(dtv / nsub);
+    for (int sub = 0; sub < nsub; ++sub) {
+      if (sub == 1)
+        for (int q = 0; q < n; ++q) {
+          tab.e[q].s_hi = tab.e[q].o_hi;
+          tab.e[q].s_lo = tab.e[q].o_lo;
+        }
+      OG_TRY(launch_slots<og::SM_STAGE>(dr, tab, n, og::R_STATE, og::R_ZA, h / T(4)));
+      OG_TRY(launch_slots<og::SM_STAGE>(dr, tab, n, og::R_ZA, og::R_ZB, h / T(3)));
+      OG_TRY(launch_slots<og::SM_STAGE>(dr, tab, n, og::R_ZB, og::R_ZA, h / T(2)));
+      OG_TRY(launch_slots<og::SM_FINAL>(dr, tab, n, og::R_ZA, og::R_OUT, h));
+    }
+    return OG_OK;
+  }
+
+  og_status run_group(int dr, std::vector<Op>& ops) {
+    // same slice length in one launch: sort by dt, then chunks of MAXSLOT
+    std::stable_sort(ops.begin(), ops.end(),
+                     [&](const Op& a, const Op& b) { return slots[a.slot].r.dt < slots[b.slot].r.dt; });
+    size_t i = 0;
+    while (i < ops.size()) {
+      const double dtv = slots[ops[i].slot].r.dt;
+      size_t k = i;
+      while (k < ops.size() && k - i < (size_t)og::MAXSLOT && slots[ops[k].slot].r.dt == dtv) ++k;
+      OG_TRY(run_chunk(dr, ops, i, k, dtv));
+      i = k;
+    }
+    return OG_OK;
+  }
+
+  og_status serve_step(int max_slices, hipStream_t s, std::vector<long>& done) override {
+    st = s;
+    for (int it = 0; it < max_slices && !slots.empty(); ++it) {
+      std::vector<Op> fwd, adj;
+      for (size_t i = 0; i < slots.size(); ++i) {
+        Slot& sl = slots[i];
+        for (;;) {
+          if (!sl.inited) {
+            OG_TRY(load1(sl.r.rho0, E, sl.cur_hi, sl.cur_lo, s));
+            sl.inited = true;
+            sl.phase = PH_FWD;
+            sl.j = 0;
+          }
+          if (sl.phase == PH_FWD) {
+            if (sl.j == sl.r.n_t) {
+              og::cost_kernel<T><<<1, 256, 0, s>>>(static_cast<const double*>(sl.r.sigma), sl.cur_hi, sl.cur_lo, E, d,
+                                                  sl.r.phi);
+              OG_CHECK_LAUNCH();
+              OG_TRY(load1(sl.r.sigma, 0, sl.lam_hi, sl.lam_lo, s));
+              sl.seg = sl.n_seg - 1;
+              OG_TRY(start_segment(sl, s));
+              continue;
+            }
+            if (sl.j % sl.S == 0) OG_TRY(copy1(sl.ck(sl.j / sl.S), sl.ckl(sl.j / sl.S), sl.cur_hi, sl.cur_lo, s));
+            fwd.push_back(Op{(int)i, sl.j, sl.cur_hi, sl.cur_lo, sl.cur_hi, sl.cur_lo, nullptr});
+            break;
+          }
+          if (sl.phase == PH_RECOMP) {
+            if (sl.jj == sl.n) {
+              sl.phase = PH_ADJ;
+              sl.jj = sl.n - 1;
+              continue;
+            }
+            fwd.push_back(Op{(int)i, sl.seg * sl.S + sl.jj, sl.sg(sl.jj), sl.sgl(sl.jj), sl.sg(sl.jj + 1),
+                             sl.sgl(sl.jj + 1), nullptr});
+            break;
+          }
+          if (sl.phase == PH_ADJ) {
+            if (sl.jj < 0) {
+              if (--sl.seg >= 0) {
+                OG_TRY(start_segment(sl, s));
+                continue;
+              }
+              if (K > 0) {
+                const long nn = (long)sl.r.n_t * K;
+                og::reduce_partials_kernel<<<dim3((unsigned)((nn + 255) / 256)), 256, 0, s>>>(sl.part, sl.r.n_t, K,
+                                                                                              sl.r.grad);
+                OG_CHECK_LAUNCH();
+              }
+              sl.phase = PH_DONE;
+              break;
+            }
+            adj.push_back(Op{(int)i, sl.seg * sl.S + sl.jj, sl.lam_hi, sl.lam_lo, sl.lam_hi, sl.lam_lo,
+                             sl.sg(sl.jj + 1)});
+            break;
+          }
+          break;
+        }
+      }
+      if (!fwd.empty()) OG_TRY(run_group(FWD, fwd));
+      if (!adj.empty()) OG_TRY(run_group(ADJ, adj));
+      for (const Op& o : fwd) {
+        Slot& sl = slots[o.slot];
+        if (sl.phase == PH_FWD)
+          ++sl.j;
+        else
+          ++sl.jj;
+      }
+      for (const Op& o : adj) --slots[o.slot].jj;
+      // retire finished requests (order of completion = order of admission within a step)
+      std::vector<Slot> keep;
+      keep.reserve(slots.size());
+      for (Slot& sl : slots) {
+        if (sl.phase == PH_DONE)
+          done.push_back(sl.r.tag);
+        else
+          keep.push_back(sl);
+      }
+      slots.swap(keep);
+    }
     return OG_OK;
   }
 };
@@ -953,7 +1222,7 @@ og_status og_create(og_ctx** out, int d, int K, int J, const void* H0p, const vo
   }
 
   hipError_t e1 = hipMalloc((void**)&ctx->status_dev, 256);
-  hipError_t e2 = hipMalloc((void**)&ctx->umax_dev, 256);
+  hipError_t e2 = hipMalloc((void**)&ctx->umax_dev, sizeof(double) * kUmaxBlocks * og::MAXK);
   if (e1 != hipSuccess || e2 != hipSuccess) {
     og_destroy(ctx);
     return fail(OG_ERR_DEVICE, "hipMalloc of context scratch failed");
@@ -998,6 +1267,49 @@ size_t og_workspace_bytes(const og_ctx* ctx, int B, int n_t) {
   return ctx->eng->ws_bytes(B, n_t);
 }
 
+// RK4 stability of the step h = dt / n_sub for controls u (rows x K): reads
+// max|u_k| back (one sync), bounds the spectral span of H = H0 + sum u_k H_k
+// by Gershgorin discs (or twice the Frobenius norms) and the dissipative
+// extent by 2 sum gamma ||c^dag c||_inf; the imaginary-axis limit of classical
+// RK4 is 2 sqrt(2) and the real-axis limit 2.785.
+static og_status check_stability(og_ctx* ctx, const double* u, long rows, double dt, hipStream_t st) {
+  const int K = ctx->K, d = ctx->d;
+  std::vector<double> um(K, 0.0);
+  if (K > 0) {
+    const int nblk = kUmaxBlocks;
+    og::umax_kernel<<<nblk, 256, 0, st>>>(u, rows, K, ctx->umax_dev);
+    OG_CHECK_LAUNCH();
+    std::vector<double> part((size_t)nblk * K);
+    OG_HIP(hipMemcpyAsync(part.data(), ctx->umax_dev, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    OG_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < K; ++k)
+      for (int p = 0; p < nblk; ++p) {
+        const double v = part[(size_t)p * K + k];
+        if (!std::isfinite(v)) return fail(OG_ERR_ARG, "non-finite control");
+        um[k] = std::max(um[k], v);
+      }
+  }
+  double hi = -1e300, lo = 1e300, frob = ctx->h0_frob;
+  for (int i = 0; i < d; ++i) {
+    double r = ctx->h0_rad[i];
+    for (int k = 0; k < K; ++k) r += um[k] * ctx->hk_gersh[(size_t)k * d + i];
+    hi = std::max(hi, ctx->h0_diag[i] + r);
+    lo = std::min(lo, ctx->h0_diag[i] - r);
+  }
+  for (int k = 0; k < K; ++k) frob += um[k] * ctx->hk_frob[k];
+  const double span = std::min(hi - lo, 2.0 * frob);
+  const double h = dt / ctx->opt.n_sub;
+  if (h * span > 2.83 || h * ctx->diss_bound > 2.78) {
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "RK4 step h=%g outside the stability bound: h*span(H)=%.3f (limit 2.83), h*dissipation=%.3f (limit "
+             "2.78); raise n_sub",
+             h, h * span, h * ctx->diss_bound);
+    return fail(OG_ERR_UNSTABLE_DT, buf);
+  }
+  return OG_OK;
+}
+
 og_status og_forward(og_ctx* ctx, int B, int n_t, double dt, const double* u, const void* rho0, void* rhoT,
                      void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
@@ -1009,38 +1321,9 @@ og_status og_forward(og_ctx* ctx, int B, int n_t, double dt, const double* u, co
   if (!ws) return fail(OG_ERR_WORKSPACE, "workspace is NULL");
   if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(OG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int K = ctx->K, d = ctx->d;
   ctx->phase = 0;
   OG_HIP(hipMemsetAsync(ctx->status_dev, 0, sizeof(int), st));
-  if (ctx->opt.validate && K > 0) {
-    og::umax_kernel<<<1, 256, 0, st>>>(u, (long)B * n_t, K, ctx->umax_dev);
-    OG_CHECK_LAUNCH();
-    std::vector<double> um(K);
-    OG_HIP(hipMemcpyAsync(um.data(), ctx->umax_dev, K * sizeof(double), hipMemcpyDeviceToHost, st));
-    OG_HIP(hipStreamSynchronize(st));
-    for (int k = 0; k < K; ++k)
-      if (!std::isfinite(um[k])) return fail(OG_ERR_ARG, "non-finite control");
-    double hi = -1e300, lo = 1e300, frob = ctx->h0_frob;
-    for (int i = 0; i < d; ++i) {
-      double r = ctx->h0_rad[i];
-      for (int k = 0; k < K; ++k) r += um[k] * ctx->hk_gersh[(size_t)k * d + i];
-      hi = std::max(hi, ctx->h0_diag[i] + r);
-      lo = std::min(lo, ctx->h0_diag[i] - r);
-    }
-    for (int k = 0; k < K; ++k) frob += um[k] * ctx->hk_frob[k];
-    const double span = std::min(hi - lo, 2.0 * frob);
-    const double h = dt / ctx->opt.n_sub;
-    if (h * span > 2.83 || h * ctx->diss_bound > 2.78) {
-      char buf[256];
-      snprintf(buf, sizeof buf,
-               "RK4 step h=%g outside the stability bound: h*span(H)=%.3f (limit 2.83), h*dissipation=%.3f (limit "
-               "2.78); raise n_sub",
-               h, h * span, h * ctx->diss_bound);
-      return fail(OG_ERR_UNSTABLE_DT, buf);
-    }
-  } else {
-    (void)d;
-  }
+  if (ctx->opt.validate) OG_TRY(check_stability(ctx, u, (long)B * n_t, dt, st));
   OG_TRY(ctx->eng->forward(B, n_t, dt, u, rho0, rhoT, ws, ws_bytes, st));
   ctx->phase = 1;
   return OG_OK;
@@ -1077,6 +1360,60 @@ og_status og_gradient(og_ctx* ctx, double* grad, void* stream) {
     OG_HIP(hipStreamSynchronize(st));
     if (flag) return fail(OG_ERR_NONFINITE, "a propagated state became non-finite");
   }
+  return OG_OK;
+}
+
+og_status og_server_create(og_server** out, og_ctx* ctx, int max_active) {
+  g_err.clear();
+  if (!out || !ctx || !ctx->eng) return fail(OG_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (max_active < 1 || max_active > 65536) return fail(OG_ERR_ARG, "max_active must be in [1, 65536]");
+  if (ctx->path != OG_PATH_BANDED) return fail(OG_ERR_SHAPE, "serving needs the banded path");
+  ctx->eng->serve_clear();
+  og_server* s = new og_server();
+  s->ctx = ctx;
+  s->max_active = max_active;
+  *out = s;
+  return OG_OK;
+}
+
+og_status og_server_submit(og_server* s, const og_request* r, void* stream) {
+  g_err.clear();
+  if (!s || !r) return fail(OG_ERR_ARG, "NULL argument");
+  og_ctx* ctx = s->ctx;
+  if (r->n_t < 1) return fail(OG_ERR_ARG, "n_t must be >= 1");
+  if (!(r->dt > 0.0) || !std::isfinite(r->dt)) return fail(OG_ERR_ARG, "dt must be finite and > 0");
+  if ((ctx->K > 0 && (!r->u || !r->grad)) || !r->rho0 || !r->sigma || !r->phi)
+    return fail(OG_ERR_ARG, "request pointer is NULL");
+  if (!r->ws || (reinterpret_cast<uintptr_t>(r->ws) & 255) != 0)
+    return fail(OG_ERR_WORKSPACE, "request workspace NULL or not 256-byte aligned");
+  if (ctx->eng->serve_active() >= s->max_active) return fail(OG_ERR_WORKSPACE, "server full");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (ctx->opt.validate) OG_TRY(check_stability(ctx, r->u, r->n_t, r->dt, st));
+  return ctx->eng->serve_submit(*r, st);
+}
+
+og_status og_server_step(og_server* s, int max_slices, void* stream) {
+  g_err.clear();
+  if (!s) return fail(OG_ERR_ARG, "NULL server");
+  if (max_slices < 1) return fail(OG_ERR_ARG, "max_slices must be >= 1");
+  return s->ctx->eng->serve_step(max_slices, static_cast<hipStream_t>(stream), s->completed);
+}
+
+int og_server_active(const og_server* s) { return s ? s->ctx->eng->serve_active() : 0; }
+
+int og_server_completed(og_server* s, long* tags, int max_tags) {
+  if (!s || !tags || max_tags < 1) return 0;
+  const int n = std::min<int>(max_tags, (int)s->completed.size());
+  for (int i = 0; i < n; ++i) tags[i] = s->completed[i];
+  s->completed.erase(s->completed.begin(), s->completed.begin() + n);
+  return n;
+}
+
+og_status og_server_destroy(og_server* s) {
+  if (!s) return OG_OK;
+  s->ctx->eng->serve_clear();
+  delete s;
   return OG_OK;
 }
 

@@ -126,9 +126,12 @@ __device__ __forceinline__ void two_sum_update(T& hi, T& lo, T delta) {
 }
 
 // Write the 32 x 32 tile held in v[4] (rows ty + 8q, column tx) to out at
-// (I0, J0) and its conjugate transpose at (J0, I0); on a diagonal tile the
-// lower triangle is taken from the conjugated upper one.
-template <typename T>
+// (I0, J0) and, with MIRROR, its conjugate transpose at (J0, I0); on a
+// diagonal tile the lower triangle is taken from the conjugated upper one.
+// Without MIRROR only the upper-triangular tiles are written: used for the
+// compensation term of the state, which is read at those tiles only (the
+// readers of whole matrices take a lower tile from its mirror).
+template <typename T, bool MIRROR = true>
 __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d, int I0, int J0,
                                                 const cpx<T> (&v)[4], cpx<T> (*tile)[TS + 1], int tx,
                                                 int ty) {
@@ -146,7 +149,7 @@ __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d,
       out[(long)i * d + j] = z;
     }
   }
-  if (!diag) {
+  if (MIRROR && !diag) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int r = ty + 8 * q;
@@ -156,9 +159,40 @@ __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d,
   }
 }
 
+// Element e = i d + j of a compensation matrix kept on the upper tiles only.
+template <typename T>
+__device__ __forceinline__ cpx<T> lo_at(const cpx<T>* __restrict__ lo, int d, long e) {
+  const int i = (int)(e / d), j = (int)(e - (long)i * d);
+  return (i / TS > j / TS) ? conjg(lo[(long)j * d + i]) : lo[e];
+}
+
+// Per-problem addresses of one stage launch.
+template <typename T>
+struct ProbPtr {
+  const cpx<T>* in;
+  const cpx<T>* shi;
+  const cpx<T>* slo;
+  cpx<T>* ohi;
+  cpx<T>* olo;
+  const cpx<T>* ex[3];
+};
+
+template <typename T>
+__device__ __forceinline__ ProbPtr<T> resolve_strided(const StageIO<T>& io, int b) {
+  ProbPtr<T> P;
+  P.in = io.in + (long)b * io.in_s;
+  P.shi = io.shi ? io.shi + (long)b * io.s_s : nullptr;
+  P.slo = io.slo ? io.slo + (long)b * io.s_s : nullptr;
+  P.ohi = io.ohi + (long)b * io.o_s;
+  P.olo = io.olo ? io.olo + (long)b * io.o_s : nullptr;
+#pragma unroll
+  for (int x = 0; x < 3; ++x) P.ex[x] = io.ex[x] ? io.ex[x] + (long)b * io.ex_s : nullptr;
+  return P;
+}
+
 template <typename T, int MODE>
-__device__ __forceinline__ void stage_epilogue(const StageIO<T>& io, int d, int b, int I0, int J0,
-                                               const cpx<T> (&val)[4], cpx<T> (*tile)[TS + 1], int tx,
+__device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int nex, int* status, int d, int I0,
+                                               int J0, const cpx<T> (&val)[4], cpx<T> (*tile)[TS + 1], int tx,
                                                int ty) {
   cpx<T> oh[4], ol[4];
   bool bad = false;
@@ -170,18 +204,18 @@ __device__ __forceinline__ void stage_epilogue(const StageIO<T>& io, int d, int 
     if (i < d && j < d) {
       const long e = (long)i * d + j;
       if (MODE == SM_SCALE) {
-        oh[q] = cscale(io.coef, val[q]);
+        oh[q] = cscale(coef, val[q]);
       } else if (MODE == SM_STAGE) {
         // the stage input is rounded to T anyway: the compensation term of
         // the state changes it by at most one ulp and is not read here
-        const cpx<T> h = io.shi[(long)b * io.s_s + e];
-        oh[q] = mkc<T>(h.re + io.coef * val[q].re, h.im + io.coef * val[q].im);
+        const cpx<T> h = P.shi[e];
+        oh[q] = mkc<T>(h.re + coef * val[q].re, h.im + coef * val[q].im);
       } else {  // SM_FINAL
-        cpx<T> dl = cscale(io.coef, val[q]);
-        for (int x = 0; x < io.nex; ++x) dl = cadd(dl, io.ex[x][(long)b * io.ex_s + e]);
-        cpx<T> h = io.shi[(long)b * io.s_s + e];
-        if (io.slo) {
-          cpx<T> l = io.slo[(long)b * io.s_s + e];
+        cpx<T> dl = cscale(coef, val[q]);
+        for (int x = 0; x < nex; ++x) dl = cadd(dl, P.ex[x][e]);
+        cpx<T> h = P.shi[e];
+        if (P.slo) {
+          cpx<T> l = P.slo[e];
           two_sum_update(h.re, l.re, dl.re);
           two_sum_update(h.im, l.im, dl.im);
           ol[q] = l;
@@ -197,9 +231,9 @@ __device__ __forceinline__ void stage_epilogue(const StageIO<T>& io, int d, int 
       }
     }
   }
-  if (MODE == SM_FINAL && bad) *io.status = 1;
-  write_herm_tile<T>(io.ohi + (long)b * io.o_s, d, I0, J0, oh, tile, tx, ty);
-  if (MODE == SM_FINAL && io.olo) write_herm_tile<T>(io.olo + (long)b * io.o_s, d, I0, J0, ol, tile, tx, ty);
+  if (MODE == SM_FINAL && bad) *status = 1;
+  write_herm_tile<T>(P.ohi, d, I0, J0, oh, tile, tx, ty);
+  if (MODE == SM_FINAL && P.olo) write_herm_tile<T, false>(P.olo, d, I0, J0, ol, tile, tx, ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,8 +241,8 @@ __device__ __forceinline__ void stage_epilogue(const StageIO<T>& io, int d, int 
 //   L(Y)_ij = sum_a A_a(i) Y[i + o_a, j] + sum_a Y[i, j + o_a] conj(A_a(j))
 //           + sum_t Dl_t(i) conj(Dr_t(j)) Y[i + dp_t, j + dq_t]
 // i.e. A Y + Y A^dag + sum_m gamma_m C_m Y C_m^dag in diagonal storage.
-// grid.x = B * ntile (upper-triangular tiles), block = 256 threads, each
-// thread owns rows ty, ty+8, ty+16, ty+24 and column tx of the tile.
+// One block computes one upper-triangular 32 x 32 tile of one problem with
+// 256 threads; each thread owns rows ty, ty+8, ty+16, ty+24 and column tx.
 // NA / ND bound the number of diagonals / dissipator taps at compile time so
 // that every tap load of an element is issued before the arithmetic; rows
 // and columns outside the matrix are clamped, which is exact because the
@@ -227,11 +261,8 @@ __device__ __forceinline__ cpx<T> ldm(const cpx<T>* __restrict__ base, unsigned 
 // Diagonal coefficients of A(u_j) = A0 + sum_k u[b, j, k] Ak for every
 // problem of the batch, once per slice: coef[b][a][i] = A(u_j)[i, i + o_a].
 template <typename T>
-__global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, int K,
-                                                        const double* __restrict__ u, long u_bs, int jslice,
-                                                        cpx<T>* __restrict__ coef) {
-  const int b = blockIdx.y;
-  const double* ub = u + (long)b * u_bs + (long)jslice * K;
+__device__ __forceinline__ void coef_body(const BandOps<T>& ops, int d, int K, const double* __restrict__ ub,
+                                          cpx<T>* __restrict__ out) {
   const int n = ops.nA * d;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     cpx<T> v = ops.A0[e];
@@ -241,28 +272,29 @@ __global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, i
       v.re += uk * h.re;
       v.im += uk * h.im;
     }
-    coef[(long)b * n + e] = v;
+    out[e] = v;
   }
 }
 
-// EXACT: the operator set has exactly NA diagonals and ND taps (no
-// predication); otherwise NA / ND are upper bounds of ops.nA / ops.nD.
+template <typename T>
+__global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, int K,
+                                                        const double* __restrict__ u, long u_bs, int jslice,
+                                                        cpx<T>* __restrict__ coef) {
+  const int b = blockIdx.y;
+  coef_body(ops, d, K, u + (long)b * u_bs + (long)jslice * K, coef + (long)b * ops.nA * d);
+}
+
 template <typename T, int MODE, int NA, int ND, bool EXACT>
-__global__ __launch_bounds__(256) void band_stage_kernel(BandOps<T> ops, StageIO<T> io,
-                                                         const int2* __restrict__ tiles, int ntile, int d,
-                                                         const cpx<T>* __restrict__ coef) {
+__device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const ProbPtr<T>& P,
+                                                const cpx<T>* __restrict__ cb, T coef, int nex, int* status,
+                                                int I0, int J0, int d) {
   __shared__ cpx<T> cR[NA][TS];
   __shared__ cpx<T> cC[NA][TS];
   __shared__ cpx<T> dR[ND][TS];
   __shared__ cpx<T> dC[ND][TS];
   __shared__ cpx<T> tile[TS][TS + 1];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = L / ntile, t = L - b * ntile;
-  const int2 tt = tiles[t];
-  const int I0 = tt.x * TS, J0 = tt.y * TS;
   const int nA = EXACT ? NA : ops.nA, nD = EXACT ? ND : ops.nD;
-  const cpx<T>* __restrict__ cb = coef + (long)b * nA * d;
   for (int e = tid; e < 2 * (nA + nD) * TS; e += 256) {
     const int side = e / ((nA + nD) * TS);
     const int rem = e - side * (nA + nD) * TS;
@@ -288,7 +320,7 @@ __global__ __launch_bounds__(256) void band_stage_kernel(BandOps<T> ops, StageIO
     }
   }
   __syncthreads();
-  const cpx<T>* __restrict__ Y = io.in + (long)b * io.in_s;
+  const cpx<T>* __restrict__ Y = P.in;
   const int dm = d - 1;
   const int jc = min(J0 + tx, dm);
   int colA[NA], colD[ND];
@@ -324,7 +356,75 @@ __global__ __launch_bounds__(256) void band_stage_kernel(BandOps<T> ops, StageIO
       if (EXACT || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[s]);
     val[q] = acc;
   }
-  stage_epilogue<T, MODE>(io, d, b, I0, J0, val, tile, tx, ty);
+  stage_epilogue<T, MODE>(P, coef, nex, status, d, I0, J0, val, tile, tx, ty);
+}
+
+// Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
+template <typename T, int MODE, int NA, int ND, bool EXACT>
+__global__ __launch_bounds__(256) void band_stage_kernel(BandOps<T> ops, StageIO<T> io,
+                                                         const int2* __restrict__ tiles, int ntile, int d,
+                                                         const cpx<T>* __restrict__ coef) {
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / ntile, t = L - b * ntile;
+  const int2 tt = tiles[t];
+  const int nA = EXACT ? NA : ops.nA;
+  band_stage_body<T, MODE, NA, ND, EXACT>(ops, resolve_strided(io, b), coef + (long)b * nA * d, io.coef, io.nex,
+                                         io.status, tt.x * TS, tt.y * TS, d);
+}
+
+// ---------------------------------------------------------------------------
+// Slot-table launches (continuous batching): every problem of the launch is
+// an independent request with its own buffers.  The table travels in the
+// kernel arguments.  Stage operand / output are chosen per launch by role.
+// ---------------------------------------------------------------------------
+constexpr int MAXSLOT = 32;
+enum SlotRole : int { R_STATE = 0, R_ZA = 1, R_ZB = 2, R_OUT = 3 };
+
+template <typename T>
+struct SlotEntry {
+  const cpx<T>* s_hi;  // state read
+  const cpx<T>* s_lo;
+  cpx<T>* o_hi;        // state written by the final stage
+  cpx<T>* o_lo;
+  cpx<T>* za;          // stage buffers
+  cpx<T>* zb;
+  cpx<T>* coef;        // diagonal coefficients of this slot's slice
+  const double* urow;  // u[j, :] of this slot's slice
+};
+
+template <typename T>
+struct SlotTable {
+  SlotEntry<T> e[MAXSLOT];
+};
+
+template <typename T>
+__device__ __forceinline__ const cpx<T>* role_ptr(const SlotEntry<T>& s, int role) {
+  return role == R_STATE ? s.s_hi : role == R_ZA ? s.za : role == R_ZB ? s.zb : s.o_hi;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void band_coef_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int d, int K) {
+  const SlotEntry<T>& s = tab.e[blockIdx.y];
+  coef_body(ops, d, K, s.urow, s.coef);
+}
+
+template <typename T, int MODE, int NA, int ND>
+__global__ __launch_bounds__(256) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
+                                                               int out_role, T coef, int* status,
+                                                               const int2* __restrict__ tiles, int ntile,
+                                                               int d) {
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / ntile, t = L - b * ntile;
+  const int2 tt = tiles[t];
+  const SlotEntry<T>& s = tab.e[b];
+  ProbPtr<T> P;
+  P.in = role_ptr(s, in_role);
+  P.shi = s.s_hi;
+  P.slo = s.s_lo;
+  P.ohi = const_cast<cpx<T>*>(role_ptr(s, out_role));
+  P.olo = out_role == R_OUT ? s.o_lo : nullptr;
+  P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
+  band_stage_body<T, MODE, NA, ND, false>(ops, P, s.coef, coef, 0, status, tt.x * TS, tt.y * TS, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +457,7 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
     const int i = I0 + r, j = J0 + tx;
     val[q] = (i < d && j < d) ? cadd(Xb[(long)i * d + j], conjg(tT[tx][r])) : mkc<T>(0, 0);
   }
-  stage_epilogue<T, MODE>(io, d, b, I0, J0, val, tile, tx, ty);
+  stage_epilogue<T, MODE>(resolve_strided(io, b), io.coef, io.nex, io.status, d, I0, J0, val, tile, tx, ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,16 +637,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // phi[b] = Re Tr(sigma rho_b) = sum_e Re(sigma_e conj(rho_e)) (rho Hermitian).
 template <typename T>
 __global__ __launch_bounds__(256) void cost_kernel(const double* __restrict__ sigma, const cpx<T>* __restrict__ hi,
-                                                   const cpx<T>* __restrict__ lo, long s_s, long n,
+                                                   const cpx<T>* __restrict__ lo, long s_s, int d,
                                                    double* __restrict__ phi) {
   __shared__ double sh[256];
   const int b = blockIdx.x;
+  const long n = (long)d * d;
   double acc = 0.0;
   for (long e = threadIdx.x; e < n; e += 256) {
     const cpx<T> h = hi[(long)b * s_s + e];
     double rr = (double)h.re, ri = (double)h.im;
     if (lo) {
-      const cpx<T> l = lo[(long)b * s_s + e];
+      const cpx<T> l = lo_at(lo + (long)b * s_s, d, e);
       rr += (double)l.re;
       ri += (double)l.im;
     }
@@ -599,54 +700,80 @@ __device__ __forceinline__ void write_partials(double (*sh)[MAXK], const double*
   }
 }
 
+// acc[k] += cf * 2-less Im-part sum over the rows [a0, a1) of chunk ch.
+template <typename T, int NH>
+__device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, const cpx<T>* __restrict__ Lm, double cf,
+                                              const HBand<T>& hb, int K, int d, int a0, int a1, double* acc) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nH = hb.nH, dm = d - 1;
+  for (int a = a0 + wave; a < a1; a += 4) {
+    // this lane's part of the row products P_t = sum_c X[a + o_t, c] conj(L[a, c])
+    cpx<T> P[NH];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) P[t] = mkc<T>(0, 0);
+    for (int c0 = 0; c0 < d; c0 += 64) {
+      const int c = c0 + lane;
+      const int cc = min(c, dm);
+      cpx<T> l = ldm(Lm, __umul24(a, d) + cc);
+      if (c > dm) l = mkc<T>(0, 0);
+      cpx<T> x[NH];
+#pragma unroll
+      for (int t = 0; t < NH; ++t)
+        if (t < nH) x[t] = ldm(X, __umul24(clampi(a + hb.offH[t], dm), d) + cc);
+#pragma unroll
+      for (int t = 0; t < NH; ++t)
+        if (t < nH) cfmac(P[t], x[t], l);
+    }
+    // weight by H_k[a, a + o_t] once per row
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < NH; ++t)
+        if (t < nH) {
+          const cpx<T> h = hb.Hd[((long)k * nH + t) * d + a];
+          s += (double)h.re * (double)P[t].im + (double)h.im * (double)P[t].re;
+        }
+      acc[k] += cf * s;
+    }
+  }
+}
+
 template <typename T, int NH>
 __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBand<T> hb, int K, int d,
                                                             double* __restrict__ part, long n_t, int jslice,
                                                             int accumulate) {
   __shared__ double sh[4][MAXK];
   const int ch = blockIdx.x, b = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int a0 = (int)((long)d * ch / NCH), a1 = (int)((long)d * (ch + 1) / NCH);
-  const int nH = hb.nH, dm = d - 1;
   double acc[MAXK];
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
-  for (int p = 0; p < pa.np; ++p) {
-    const cpx<T>* __restrict__ X = pa.X[p] + (long)b * pa.x_s;
-    const cpx<T>* __restrict__ Lm = pa.L[p] + (long)b * pa.l_s;
-    const double cf = pa.coef[p];
-    for (int a = a0 + wave; a < a1; a += 4) {
-      // this lane's part of the row products P_t = sum_c X[a + o_t, c] conj(L[a, c])
-      cpx<T> P[NH];
-#pragma unroll
-      for (int t = 0; t < NH; ++t) P[t] = mkc<T>(0, 0);
-      for (int c0 = 0; c0 < d; c0 += 64) {
-        const int c = c0 + lane;
-        const int cc = min(c, dm);
-        cpx<T> l = ldm(Lm, __umul24(a, d) + cc);
-        if (c > dm) l = mkc<T>(0, 0);
-        cpx<T> x[NH];
-#pragma unroll
-        for (int t = 0; t < NH; ++t)
-          if (t < nH) x[t] = ldm(X, __umul24(clampi(a + hb.offH[t], dm), d) + cc);
-#pragma unroll
-        for (int t = 0; t < NH; ++t)
-          if (t < nH) cfmac(P[t], x[t], l);
-      }
-      // weight by H_k[a, a + o_t] once per row
-      for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < NH; ++t)
-          if (t < nH) {
-            const cpx<T> h = hb.Hd[((long)k * nH + t) * d + a];
-            s += (double)h.re * (double)P[t].im + (double)h.im * (double)P[t].re;
-          }
-        acc[k] += cf * s;
-      }
-    }
-  }
+  for (int p = 0; p < pa.np; ++p)
+    contract_rows<T, NH>(pa.X[p] + (long)b * pa.x_s, pa.L[p] + (long)b * pa.l_s, pa.coef[p], hb, K, d, a0, a1,
+                         acc);
   write_partials(sh, acc, K, part, (((long)b * n_t + jslice) * NCH + ch) * K, accumulate);
+}
+
+// Slot-table variant (first-order gradient of one slice per slot): partials
+// of slot b go to out[b][chunk][k].
+template <typename T>
+struct PairSlots {
+  const cpx<T>* X[MAXSLOT];
+  const cpx<T>* L[MAXSLOT];
+  double* out[MAXSLOT];
+};
+
+template <typename T, int NH>
+__global__ __launch_bounds__(256) void band_contract_slots_kernel(PairSlots<T> ps, double cf, HBand<T> hb, int K,
+                                                                  int d) {
+  __shared__ double sh[4][MAXK];
+  const int ch = blockIdx.x, b = blockIdx.y;
+  const int a0 = (int)((long)d * ch / NCH), a1 = (int)((long)d * (ch + 1) / NCH);
+  double acc[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
+  contract_rows<T, NH>(ps.X[b], ps.L[b], cf, hb, K, d, a0, a1, acc);
+  write_partials(sh, acc, K, ps.out[b], (long)ch * K, 0);
 }
 
 // Dense contraction: W_p = X_p L_p already formed by the GEMM; with HT_k the
@@ -708,14 +835,15 @@ __global__ __launch_bounds__(256) void load_state_kernel(const double* __restric
 
 template <typename T>
 __global__ __launch_bounds__(256) void store_state_kernel(const cpx<T>* __restrict__ hi,
-                                                          const cpx<T>* __restrict__ lo, long s_s, long n,
+                                                          const cpx<T>* __restrict__ lo, long s_s, int d,
                                                           double* __restrict__ dst) {
   const int b = blockIdx.y;
+  const long n = (long)d * d;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
     const cpx<T> h = hi[(long)b * s_s + e];
     double xr = h.re, xi = h.im;
     if (lo) {
-      const cpx<T> l = lo[(long)b * s_s + e];
+      const cpx<T> l = lo_at(lo + (long)b * s_s, d, e);
       xr += (double)l.re;
       xi += (double)l.im;
     }
@@ -724,13 +852,14 @@ __global__ __launch_bounds__(256) void store_state_kernel(const cpx<T>* __restri
   }
 }
 
-// max_{b, j} |u[b, j, k]| for every k (one block).
+// Partial maxima max |u[r, k]| over the rows r = blockIdx.x, blockIdx.x +
+// gridDim.x, ... for every k: out[blockIdx.x * K + k].  A NaN propagates.
 __global__ __launch_bounds__(256) void umax_kernel(const double* __restrict__ u, long n_rows, int K,
                                                    double* __restrict__ out) {
   __shared__ double sh[256];
   for (int k = 0; k < K; ++k) {
     double m = 0.0;
-    for (long r = threadIdx.x; r < n_rows; r += 256) {
+    for (long r = (long)blockIdx.x * 256 + threadIdx.x; r < n_rows; r += (long)gridDim.x * 256) {
       const double a = fabs(u[r * K + k]);
       m = (a != a || m != m) ? a + m : fmax(m, a);  // a NaN control propagates
     }
@@ -744,7 +873,7 @@ __global__ __launch_bounds__(256) void umax_kernel(const double* __restrict__ u,
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = sh[0];
+    if (threadIdx.x == 0) out[(long)blockIdx.x * K + k] = sh[0];
   }
 }
 
