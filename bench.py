@@ -53,7 +53,43 @@ def _parse():
     ap.add_argument("--serve-loads", default="0.8", help="offered loads as fractions of saturation")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
+                    help="c3: the headline; c4: dense random d=512 precision comparison (own JSON line)")
     return ap.parse_args()
+
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "f16x3": 2500.0}
+
+
+def dense_leg(args):
+    """Dense random d = 512 problem (K = 4, J = 4, N_t = 1000, dt = 0.005) on
+    the dense matrix-core path in float64, float32 and the two 16-bit split
+    precisions; error of problem 0 against the stored float64 oracle values.
+    Roofline of the first GEMM of every stage (X = A Y and C_m Y for all m):
+    B (1 + J) complex 512^3 products per launch, 8 d^3 real flops each; the
+    split precisions execute three 16-bit products per real product."""
+    import workloads as wl
+
+    w = wl.config_c4(n_t=args.n_t)
+    if args.batch > 1:
+        w.u = np.stack([wl.controls_uniform(8 + b, args.n_t, 4) for b in range(args.batch)])
+    gpath = os.path.join(ROOT, "tests", "golden", "c4_dense_d512_nt1000.npz")
+    golden = dict(np.load(gpath)) if os.path.exists(gpath) else None
+    args.path = "dense"
+    precs = [p for p in args.precisions.split(",") if p]
+    out = {"workload": "dense random d=512, K=4, J=4, N_t=%d, dt=0.005" % args.n_t, "batch": args.batch,
+           "path": "dense", "gradient": args.gmode, "results": {}}
+    flops = args.batch * (1 + w.J) * 8.0 * w.d ** 3
+    for prec in precs:
+        r = run_gpu(args, prec, w, golden)
+        tf = flops / (r["kern_us"] * 1e-6) / 1e12 if r["kern_us"] > 0 else None
+        executed = tf * (3 if "x3" in prec else 1) if tf else None
+        r["roofline"] = {"bound": "mfma", "kernel": "zgemm (first GEMM of each stage)", "achieved_useful": tf,
+                         "achieved_executed": executed, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                         "frac": executed / PEAK_TFLOPS[prec] if executed else None}
+        out["results"][prec] = r
+        _log(f"[c4] {prec}: {r}")
+    return out
 
 
 def serving_leg(args):
@@ -142,8 +178,8 @@ def run_gpu(args, prec, w, golden):
     g = g.cpu().numpy()
     out = dict(prec=prec, elapsed=elapsed, ms_per_step=1000 * elapsed / args.steps,
                value=B * args.steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path)
-    if golden is not None and n_t == 10000:
-        gkey = "g_grape1" if args.gmode == "grape1" else "g_exact"
+    gkey = "g_grape1" if args.gmode == "grape1" else "g_exact"
+    if golden is not None and golden[gkey].shape[0] == n_t:
         out["err_phi"] = float(abs(phi[0] - golden["phi"]) / abs(golden["phi"]))
         out["err_grad"] = float(np.linalg.norm(g[0] - golden[gkey]) / np.linalg.norm(golden[gkey]))
     p.close()
@@ -215,6 +251,9 @@ def main():
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_leg(args)}), flush=True)
+        return
+    if args.workload == "c4":
+        print(json.dumps(dense_leg(args)), flush=True)
         return
     import workloads as wl
 

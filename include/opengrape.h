@@ -64,9 +64,21 @@ typedef enum {
 
 typedef enum {
     OG_F64 = 0,                /* float64 states and arithmetic                */
-    OG_F32 = 1                 /* float32 arithmetic; states carried as a
+    OG_F32 = 1,                /* float32 arithmetic; states carried as a
                                   compensated (hi, lo) float32 pair; cost,
                                   trace and gradient sums in float64          */
+    OG_F32_SPLIT_BF16 = 2,     /* as OG_F32, but the dense-path GEMMs split
+                                  every float32 operand into two bfloat16
+                                  parts and use three bfloat16 matrix-core
+                                  products with float32 accumulation
+                                  (~16 significant bits per product)         */
+    OG_F32_SPLIT_F16 = 3       /* as OG_F32_SPLIT_BF16 with float16 parts
+                                  (~22 bits); operands are scaled by 2^8
+                                  internally, so operator and state entries
+                                  must stay below 2^7 in magnitude (larger
+                                  ones overflow and are reported as
+                                  OG_ERR_NONFINITE).  The banded path runs
+                                  the split precisions as OG_F32.            */
 } og_prec;
 
 typedef enum {

@@ -16,7 +16,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("OPENGRAPE_LIB") or os.path.join(_HERE, "libopengrape.so")
 
-PREC = {"f64": 0, "f32": 1}
+PREC = {"f64": 0, "f32": 1, "bf16x3": 2, "f16x3": 3}
 GMODE = {"grape1": 0, "exact": 1}
 PATH = {"auto": 0, "dense": 1, "banded": 2}
 PATH_NAMES = {1: "dense", 2: "banded"}

@@ -299,6 +299,22 @@ struct Engine : EngineBase {
 
   Engine(og_ctx* c) : ctx(c), d(c->d), K(c->K), J(c->J), banded(c->path == OG_PATH_BANDED), E((long)c->d * c->d) {}
 
+  // Dense GEMMs: float32/float64 matrix-core GEMM, or for the split
+  // precisions the 16-bit three-product split GEMM (float32 storage).
+  void launch_gemm(const og::GemmArgs<T>& g, dim3 grid) {
+    if constexpr (sizeof(T) == 4) {
+      if (ctx->opt.prec == OG_F32_SPLIT_BF16) {
+        og::zgemm_split_kernel<og::SPLIT_BF16><<<grid, 256, 0, st>>>(g);
+        return;
+      }
+      if (ctx->opt.prec == OG_F32_SPLIT_F16) {
+        og::zgemm_split_kernel<og::SPLIT_F16><<<grid, 256, 0, st>>>(g);
+        return;
+      }
+    }
+    og::zgemm_kernel<T><<<grid, 256, 0, st>>>(g);
+  }
+
   ~Engine() override {
     for (int s = 0; s < 2; ++s) {
       void* ps[] = {dir[s].bA0, dir[s].bAk, dir[s].bDl, dir[s].bDr, dir[s].A0, dir[s].Ak, dir[s].C, dir[s].Chat};
@@ -542,7 +558,7 @@ struct Engine : EngineBase {
     }
     const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * g.nm));
     const long pidx = ctx->prof_begin(st);
-    og::zgemm_kernel<T><<<gg, 256, 0, st>>>(g);
+    launch_gemm(g, gg);
     OG_CHECK_LAUNCH();
     ctx->prof_end(pidx, st);
     if (J > 0) {
@@ -563,7 +579,7 @@ struct Engine : EngineBase {
       h.sC[0] = E;
       h.ldc[0] = d;
       const dim3 hg((d + 63) / 64, (d + 63) / 64, (unsigned)B);
-      og::zgemm_kernel<T><<<hg, 256, 0, st>>>(h);
+      launch_gemm(h, hg);
       OG_CHECK_LAUNCH();
     }
     if (mode == og::SM_STAGE)
@@ -651,7 +667,7 @@ struct Engine : EngineBase {
       g.ldc[p] = d;
     }
     const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * np));
-    og::zgemm_kernel<T><<<gg, 256, 0, st>>>(g);
+    launch_gemm(g, gg);
     OG_CHECK_LAUNCH();
     double c[4] = {0, 0, 0, 0};
     for (int p = 0; p < np; ++p) c[p] = coefs[p];
@@ -1114,7 +1130,7 @@ og_status og_create(og_ctx** out, int d, int K, int J, const void* H0p, const vo
   og_options opt;
   og_default_options(&opt);
   if (optp) opt = *optp;
-  if (opt.prec != OG_F64 && opt.prec != OG_F32) return fail(OG_ERR_ARG, "unknown precision");
+  if (opt.prec < OG_F64 || opt.prec > OG_F32_SPLIT_F16) return fail(OG_ERR_ARG, "unknown precision");
   if (opt.gmode != OG_GRAD_GRAPE1 && opt.gmode != OG_GRAD_EXACT) return fail(OG_ERR_ARG, "unknown gradient mode");
   if (opt.path < OG_PATH_AUTO || opt.path > OG_PATH_BANDED) return fail(OG_ERR_ARG, "unknown path");
   if (opt.n_sub < 1 || opt.n_sub > 64) return fail(OG_ERR_ARG, "n_sub must be in [1, 64]");

@@ -592,6 +592,165 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
 }
 
 // ---------------------------------------------------------------------------
+// Split-precision complex GEMM for float32 operands on the 16-bit matrix
+// cores.  Every float32 x is split into x = hi + lo with hi, lo 16-bit
+// (bfloat16: 8-bit mantissas, together 16 bits; float16: 11-bit mantissas,
+// together 22 bits, operands pre-scaled by 2^8 to keep lo normal), and each
+// real product uses three v_mfma_f32_16x16x32 instructions,
+// X Y ~ Xhi Yhi + Xhi Ylo + Xlo Yhi, accumulated in float32 (the lo*lo term
+// is below the split's own rounding).  Complex products use the 4M form.
+// Block tile 64 x 64, K step 32, 256 threads (2 x 2 waves of 32 x 32).
+// Operand tiles are split once into LDS as 4 planes (re hi, re lo, im hi,
+// im lo), A as [row][k] and B transposed as [col][k], so that every MFMA
+// operand (8 consecutive k of one row / column) is one 16-byte LDS read.
+// Operand lane layout (checked on gfx950): A[l % 16][8 (l / 16) + v],
+// B[8 (l / 16) + v][l % 16], output as for the float32 16x16x4 form.
+// ---------------------------------------------------------------------------
+enum SplitKind : int { SPLIT_BF16 = 0, SPLIT_F16 = 1 };
+
+template <int KIND>
+struct Split;
+template <>
+struct Split<SPLIT_BF16> {
+  typedef __bf16 e_t;
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  static constexpr float scale = 1.0f;
+  static __device__ __forceinline__ e_t cvt(float x) { return (e_t)x; }
+  static __device__ __forceinline__ float back(e_t x) { return (float)x; }
+  static __device__ __forceinline__ Mfma<float>::acc_t mma(v8 a, v8 b, Mfma<float>::acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Split<SPLIT_F16> {
+  typedef _Float16 e_t;
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  static constexpr float scale = 256.0f;
+  static __device__ __forceinline__ e_t cvt(float x) { return (e_t)x; }
+  static __device__ __forceinline__ float back(e_t x) { return (float)x; }
+  static __device__ __forceinline__ Mfma<float>::acc_t mma(v8 a, v8 b, Mfma<float>::acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int KIND>
+__global__ __launch_bounds__(256) void zgemm_split_kernel(GemmArgs<float> g) {
+  typedef Split<KIND> S;
+  typedef typename S::e_t e_t;
+  typedef typename S::v8 v8;
+  typedef Mfma<float>::acc_t acc_t;
+  constexpr int BM = 64, BN = 64, BK = 32, KP = BK + 8;  // padded k extent
+  __shared__ __attribute__((aligned(16))) e_t As[4][BM][KP];
+  __shared__ __attribute__((aligned(16))) e_t Bs[4][BN][KP];
+  const int z = blockIdx.z;
+  const int b = z / g.nm, m = z - b * g.nm;
+  const cpx<float>* __restrict__ A = g.A[m] + (long)b * g.sA[m];
+  const cpx<float>* __restrict__ Bm = g.B[m] + (long)b * g.sB[m];
+  cpx<float>* __restrict__ C = g.C[m] + (long)b * g.sC[m];
+  const int lda = g.lda[m], ldb = g.ldb[m], ldc = g.ldc[m];
+  const int M = g.M, N = g.N, Kd = g.Kd;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const float sc = S::scale;
+  acc_t rr[2][2], ii[2][2], ri[2][2], ir[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) rr[a][c] = ii[a][c] = ri[a][c] = ir[a][c] = acc_t{0, 0, 0, 0};
+  // loaders: A rows (tid / 4) with 8 consecutive k; B column (tid % 64) with 8 consecutive k
+  const int arow = tid >> 2, akc = (tid & 3) * 8;
+  const int bcol = tid & 63, bkc = (tid >> 6) * 8;
+  for (int k0 = 0; k0 < Kd; k0 += BK) {
+    {
+      v8 p0, p1, p2, p3;
+      const int gm = m0 + arow;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int gk = k0 + akc + v;
+        const cpx<float> x = (gm < M && gk < Kd) ? A[(long)gm * lda + gk] : mkc<float>(0, 0);
+        const float xr = x.re * sc, xi = x.im * sc;
+        const e_t hr = S::cvt(xr), hi_ = S::cvt(xi);
+        p0[v] = hr;
+        p1[v] = S::cvt(xr - S::back(hr));
+        p2[v] = hi_;
+        p3[v] = S::cvt(xi - S::back(hi_));
+      }
+      *reinterpret_cast<v8*>(&As[0][arow][akc]) = p0;
+      *reinterpret_cast<v8*>(&As[1][arow][akc]) = p1;
+      *reinterpret_cast<v8*>(&As[2][arow][akc]) = p2;
+      *reinterpret_cast<v8*>(&As[3][arow][akc]) = p3;
+    }
+    {
+      v8 p0, p1, p2, p3;
+      const int gn = n0 + bcol;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int gk = k0 + bkc + v;
+        const cpx<float> x = (gk < Kd && gn < N) ? Bm[(long)gk * ldb + gn] : mkc<float>(0, 0);
+        const float xr = x.re * sc, xi = x.im * sc;
+        const e_t hr = S::cvt(xr), hi_ = S::cvt(xi);
+        p0[v] = hr;
+        p1[v] = S::cvt(xr - S::back(hr));
+        p2[v] = hi_;
+        p3[v] = S::cvt(xi - S::back(hi_));
+      }
+      *reinterpret_cast<v8*>(&Bs[0][bcol][bkc]) = p0;
+      *reinterpret_cast<v8*>(&Bs[1][bcol][bkc]) = p1;
+      *reinterpret_cast<v8*>(&Bs[2][bcol][bkc]) = p2;
+      *reinterpret_cast<v8*>(&Bs[3][bcol][bkc]) = p3;
+    }
+    __syncthreads();
+    const int kk = 8 * (lane >> 4);
+    v8 a[2][4], bb[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) {
+        a[t][pl] = *reinterpret_cast<const v8*>(&As[pl][wm + t * 16 + (lane & 15)][kk]);
+        bb[t][pl] = *reinterpret_cast<const v8*>(&Bs[pl][wn + t * 16 + (lane & 15)][kk]);
+      }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+        rr[x][y] = S::mma(a[x][0], bb[y][0], rr[x][y]);
+        rr[x][y] = S::mma(a[x][0], bb[y][1], rr[x][y]);
+        rr[x][y] = S::mma(a[x][1], bb[y][0], rr[x][y]);
+        ii[x][y] = S::mma(a[x][2], bb[y][2], ii[x][y]);
+        ii[x][y] = S::mma(a[x][2], bb[y][3], ii[x][y]);
+        ii[x][y] = S::mma(a[x][3], bb[y][2], ii[x][y]);
+        ri[x][y] = S::mma(a[x][0], bb[y][2], ri[x][y]);
+        ri[x][y] = S::mma(a[x][0], bb[y][3], ri[x][y]);
+        ri[x][y] = S::mma(a[x][1], bb[y][2], ri[x][y]);
+        ir[x][y] = S::mma(a[x][2], bb[y][0], ir[x][y]);
+        ir[x][y] = S::mma(a[x][2], bb[y][1], ir[x][y]);
+        ir[x][y] = S::mma(a[x][3], bb[y][0], ir[x][y]);
+      }
+    __syncthreads();
+  }
+  const float inv = 1.0f / (sc * sc);
+  const cpx<float> al = g.alpha, be = g.beta;
+  const bool use_beta = (be.re != 0.f || be.im != 0.f);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + x * 16 + Mfma<float>::row(lane, v);
+        const int col = n0 + wn + y * 16 + (lane & 15);
+        if (row < M && col < N) {
+          const float xr = (rr[x][y][v] - ii[x][y][v]) * inv, xi = (ri[x][y][v] + ir[x][y][v]) * inv;
+          cpx<float> o = mkc<float>(al.re * xr - al.im * xi, al.re * xi + al.im * xr);
+          if (use_beta) cfma(o, be, C[(long)row * ldc + col]);
+          C[(long)row * ldc + col] = o;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Dense generator assembly A_b = A0 + sum_k u[b, j, k] Ak[k]  (Eq. (1)).
 // ---------------------------------------------------------------------------
 template <typename T>

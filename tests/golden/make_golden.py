@@ -51,7 +51,7 @@ def c3():
                         rhoT_diag=np.diag(rhoT).real.copy(), rhoT_rows=rhoT[[0, 80, 81, 161, 239]].copy())
 
 
-def c4(n_t=100):
+def c4(n_t=1000):
     w = wl.config_c4()
     u = w.u[:n_t]
     phi, g1, ge, rhoT = _run(w, u, sparse=False, exact=False)

@@ -71,6 +71,23 @@ def test_c3_full_d240_nt10000_bench_configuration(prec):
     assert np.array_equal(phi1[0], phi[0]) and np.array_equal(grad1[0], grad[0])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16x3"])
+def test_c4_full_dense_d512_nt1000(prec):
+    """Dense random d = 512, N_t = 1000 on the matrix-core path; float64 and
+    float32 to their tolerances, the 16-bit splits reported (bounded loosely)."""
+    g = _golden("c4_dense_d512_nt1000.npz")
+    w = wl.config_c4()
+    say(f"[case] C4 full d=512 N_t=1000 prec={prec}")
+    phi, grad, rhoT, p = gpu_eval(w, w.u, prec=prec, path="dense", gmode="grape1")
+    p.close()
+    e_phi = phi_err(phi[0], float(g["phi"]))
+    e_g = relerr(grad[0], g["g_grape1"])
+    e_rows = relerr(rhoT[0][[0, 255, 511]], g["rhoT_rows"])
+    say(f"   phi {e_phi:.2e} grad {e_g:.2e} rows {e_rows:.2e}")
+    tol = TOL.get(prec, dict(phi=1e-3, grad=1e-2, rho=1e-3))
+    assert e_phi < tol["phi"] and e_g < tol["grad"] and e_rows < tol["rho"]
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_c3_full_exact_gradient(prec):
     g = _golden("c3_cqed_d240.npz")

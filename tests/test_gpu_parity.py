@@ -67,6 +67,24 @@ def test_dense_random_ragged_d70(prec, gmode):
     _check(w, u, prec, "dense", gmode, tag="dense d=70 B=2")
 
 
+@pytest.mark.parametrize("prec,bound_phi,bound_g", [("bf16x3", 1e-4, 2e-3), ("f16x3", 1e-5, 1e-4)])
+@pytest.mark.parametrize("gmode", ["grape1", "exact"])
+def test_dense_split_precision_ragged_d70(prec, bound_phi, bound_g, gmode):
+    """16-bit split GEMMs: the error is reported per result; the bounds only
+    catch a broken split (a dropped term costs orders of magnitude more)."""
+    w = wl.dense_random_problem(d=70, K=3, J=2, n_t=12, dt=0.005, seeds=(31, 32, 33, 34, 35, 36))
+    u = wl.controls_uniform(37, 12, 3, batch=2)
+    say(f"[case] dense d=70 B=2 prec={prec} gmode={gmode}")
+    phi, g, rhoT, p = gpu_eval(w, u, prec=prec, path="dense", gmode=gmode)
+    p.close()
+    for b in range(2):
+        phi_r, g_r, rho_r = oracle_eval(w, u[b], mode=gmode)
+        e_phi, e_g, e_rho = phi_err(phi[b], phi_r), relerr(g[b], g_r), relerr(rhoT[b], rho_r)
+        say(f"   b={b} rho {e_rho:.2e} phi {e_phi:.2e} grad {e_g:.2e}")
+        assert e_phi < bound_phi and e_g < bound_g
+        assert np.array_equal(rhoT[b], rhoT[b].conj().T)
+
+
 def test_n_sub_two_exact():
     w = wl.config_c1()
     _check(w, w.u[:60], "f64", "banded", "exact", n_sub=2, tag="C1 n_sub=2")
