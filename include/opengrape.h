@@ -186,6 +186,51 @@ og_status og_adjoint(og_ctx *ctx, const void *sigma, void *stream);
 og_status og_gradient(og_ctx *ctx, double *grad, void *stream);
 
 /*
+ * Multi-state index (Eq. (22), Sec. IV.B): with the B problems of the batch
+ * being the input states rho_i(0) of one control array (u repeated for every
+ * b), Phi = sum_i Tr(sigma rho_i(T)) and its gradient is the sum over the
+ * batch.  og_gradient_sum writes (accumulate = 0) or adds (accumulate = 1)
+ * sum_b dPhi_b/du to grad (device, float64 n_t x K), summed batch-major in a
+ * fixed order; adding lets the states of different operator sets (the
+ * qubit-conditioned resonator problems of Sec. IV.B) be combined from several
+ * contexts.  Requires og_adjoint; with validate = 1 syncs like og_gradient.
+ */
+og_status og_gradient_sum(og_ctx *ctx, double *grad, int accumulate, void *stream);
+
+/*
+ * Observable penalty (Eqs. (24)-(25), App. B):
+ *   Phi = Tr(sigma rho_{N_t}) - beta * sum_{n=0}^{N_t} dt Tr(A rho_n),
+ * with A = a^dag a for the photon-number penalty of the paper.  The forward
+ * sweep records Tr(A rho_n) after every slice, og_cost subtracts the sum, and
+ * the backward sweep runs the combined adjoint lambda_{N_t} = sigma - beta dt A,
+ * lambda_n = (propagated lambda_{n+1}) - beta dt A, so that one forward and one
+ * backward sweep give the gradient of the penalised index (both gradient
+ * modes).  A: host complex128 d x d, Hermitian (validate = 1 checks it).
+ * beta = 0 or A = NULL removes the penalty.  Synchronous; set it before
+ * og_forward.  Not supported by the server.
+ */
+og_status og_set_penalty(og_ctx *ctx, const void *A, double beta);
+
+/*
+ * Gaussian control filter (App. A, Eqs. (A1)-(A4)): N piecewise-constant
+ * controls u_k(j) of length dtu map to M subpixel controls of length dts,
+ *   s[b][n][k] = sum_j T[n][j] u[b][j][k],
+ *   T[n][j] = ( erf(w0 (n dts - j dtu) / 2) - erf(w0 (n dts - (j+1) dtu) / 2) ) / 2
+ * (0-based n, j; the subpixel start time as printed), w0 = omega0 the
+ * filter's reference bandwidth (omega_B / 0.5887 for a 3 dB bandwidth
+ * omega_B).  og_filter_grad applies the chain rule (Eq. (A2)):
+ *   g_u[b][j][k] = sum_n T[n][j] g_s[b][n][k],
+ * and with fix_ends = 1 returns 0 for the first and last control, which are
+ * held fixed (Fig. 1).  Arrays: device float64, row-major; 1 <= K <= 16.
+ * Run the propagation on the subpixel grid (og_forward with M slices of
+ * dts) between the two calls.
+ */
+og_status og_filter_apply(int B, int N, int M, int K, double dtu, double dts, double omega0,
+                          const double *u, double *s, void *stream);
+og_status og_filter_grad(int B, int N, int M, int K, double dtu, double dts, double omega0,
+                         int fix_ends, const double *g_s, double *g_u, void *stream);
+
+/*
  * Continuous batching (serving).  A server accepts independent requests
  * (one control array each, any N_t, on the context's operator set) while
  * others are in flight, and advances all of them together: every

@@ -38,7 +38,8 @@ EXPORTS = (
     "og_default_options", "og_create", "og_destroy", "og_path_used", "og_workspace_bytes",
     "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_profile", "og_profile_read",
     "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
-    "og_server_destroy", "og_status_string", "og_last_error",
+    "og_server_destroy", "og_status_string", "og_last_error", "og_gradient_sum", "og_set_penalty",
+    "og_filter_apply", "og_filter_grad",
 )
 
 
@@ -94,6 +95,14 @@ def load_library(path: str = LIB_PATH):
     lib.og_profile.restype = i
     lib.og_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long)]
     lib.og_profile_read.restype = i
+    lib.og_gradient_sum.argtypes = [vp, vp, i, vp]
+    lib.og_gradient_sum.restype = i
+    lib.og_set_penalty.argtypes = [vp, vp, d]
+    lib.og_set_penalty.restype = i
+    lib.og_filter_apply.argtypes = [i, i, i, i, d, d, d, vp, vp, vp]
+    lib.og_filter_apply.restype = i
+    lib.og_filter_grad.argtypes = [i, i, i, i, d, d, d, i, vp, vp, vp]
+    lib.og_filter_grad.restype = i
     lib.og_server_create.argtypes = [ctypes.POINTER(vp), vp, i]
     lib.og_server_create.restype = i
     lib.og_server_submit.argtypes = [vp, ctypes.POINTER(OgRequest), vp]
@@ -269,6 +278,46 @@ class Problem:
         phi = self.cost(sigma)
         self.adjoint(sigma)
         return phi, self.gradient()
+
+    def gradient_sum(self, out=None):
+        """sum_b dPhi_b/du (multi-state index, Eq. (22)); adds into `out` if given."""
+        n_t = self._keep.get("n_t", 1)
+        acc = out is not None
+        if out is None:
+            out = torch.empty((n_t, self.K), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_gradient_sum(self._ctx, out.data_ptr(), int(acc), _stream_ptr(self.device)))
+        return out
+
+    def set_penalty(self, A, beta):
+        """Phi -= beta dt sum_n Tr(A rho_n) (Eqs. (24)-(25)); beta = 0 removes it."""
+        a = None if A is None else _host_c128(A, (self.d, self.d))
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_set_penalty(self._ctx, None if a is None else a.ctypes.data, float(beta)))
+
+
+def filter_apply(u, N, M, dtu, dts, omega0):
+    """Subpixel controls s = T u of the Gaussian filter (App. A); u [B, N, K] float64 CUDA."""
+    lib = load_library()
+    u = u.contiguous()
+    B, K = (u.shape[0], u.shape[2]) if u.dim() == 3 else (1, u.shape[1])
+    s = torch.empty((B, M, K), dtype=torch.float64, device=u.device)
+    with torch.cuda.device(u.device):
+        _check(lib.og_filter_apply(B, N, M, K, float(dtu), float(dts), float(omega0), u.data_ptr(), s.data_ptr(),
+                                   _stream_ptr(u.device)))
+    return s if u.dim() == 3 else s[0]
+
+
+def filter_grad(g_s, N, M, dtu, dts, omega0, fix_ends=True):
+    """Chain rule dPhi/du = T^T dPhi/ds (Eq. (A2)); first / last control held fixed."""
+    lib = load_library()
+    g_s = g_s.contiguous()
+    B, K = (g_s.shape[0], g_s.shape[2]) if g_s.dim() == 3 else (1, g_s.shape[1])
+    g_u = torch.empty((B, N, K), dtype=torch.float64, device=g_s.device)
+    with torch.cuda.device(g_s.device):
+        _check(lib.og_filter_grad(B, N, M, K, float(dtu), float(dts), float(omega0), int(bool(fix_ends)),
+                                  g_s.data_ptr(), g_u.data_ptr(), _stream_ptr(g_s.device)))
+    return g_u if g_s.dim() == 3 else g_u[0]
 
 
 class OpenGrapeCost(torch.autograd.Function):

@@ -200,6 +200,7 @@ struct EngineBase {
   virtual og_status cost(const void* sigma, double* phi, hipStream_t st) = 0;
   virtual og_status adjoint(const void* sigma, hipStream_t st) = 0;
   virtual og_status gradient(double* grad, hipStream_t st) = 0;
+  virtual og_status gradient_sum(double* grad, int accumulate, hipStream_t st) = 0;
   // continuous batching (og_server_*)
   virtual og_status serve_submit(const og_request& r, hipStream_t st) = 0;
   virtual og_status serve_step(int max_slices, hipStream_t st, std::vector<long>& done) = 0;
@@ -224,6 +225,10 @@ struct og_ctx {
   double h0_frob = 0, diss_bound = 0;
   int* status_dev = nullptr;
   double* umax_dev = nullptr;
+  // observable penalty (og_set_penalty): Phi -= beta dt sum_n Tr(A rho_n)
+  double pen_beta = 0.0;
+  og::CooEntry* pen_coo = nullptr;
+  int pen_nnz = 0;
   // kernel timing samples (og_profile)
   int prof_every = 0;
   long prof_counter = 0;
@@ -296,6 +301,7 @@ struct Engine : EngineBase {
   og::cpx<T>*Aj[2], *X, *W, *Wp;
   og::cpx<T>* acoef[2];  // banded: per-slice diagonal coefficients, per direction
   double* grad;
+  double* pen;  // per-problem penalty traces Tr(A rho_n), n = 0..N_t
 
   Engine(og_ctx* c) : ctx(c), d(c->d), K(c->K), J(c->J), banded(c->path == OG_PATH_BANDED), E((long)c->d * c->d) {}
 
@@ -410,7 +416,7 @@ struct Engine : EngineBase {
   };
   enum {
     L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
-    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_COEF, L_GRAD, L_N
+    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_COEF, L_GRAD, L_PEN, L_N
   };
 
   int stride_for(int nt) const {
@@ -454,6 +460,7 @@ struct Engine : EngineBase {
     }
     // per-slice gradient partial sums, one per row chunk of the contraction
     sz[L_GRAD] = (size_t)b * nt * og::NCH * std::max(K, 1) * sizeof(double);
+    sz[L_PEN] = (size_t)b * (nt + 1) * sizeof(double);
     size_t pos = 0;
     for (int i = 0; i < L_N; ++i) {
       L.off[i] = pos;
@@ -712,6 +719,7 @@ struct Engine : EngineBase {
     acoef[0] = opt_at(L_COEF, banded);
     acoef[1] = banded ? acoef[0] + (size_t)b * og::MAXA * d : nullptr;
     grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);
+    pen = reinterpret_cast<double*>(p + L.off[L_PEN]);
     return OG_OK;
   }
 
@@ -741,9 +749,11 @@ struct Engine : EngineBase {
     n_seg = (nt + S - 1) / S;
     OG_TRY(bind(ws, b, nt));
     OG_TRY(load(rho0, E, cur_hi, cur_lo));
+    OG_TRY(penalty_trace(0));
     for (int j = 0; j < n_t; ++j) {
       if (j % S == 0) OG_TRY(copy_state(slot(ck_hi, j / S), slot(ck_lo, j / S), cur_hi, cur_lo));
       OG_TRY(rk_slice(FWD, j, cur_hi, cur_lo, cur_hi, cur_lo));
+      OG_TRY(penalty_trace(j + 1));
     }
     if (rhoT) {
       const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
@@ -753,9 +763,32 @@ struct Engine : EngineBase {
     return OG_OK;
   }
 
+  // Penalty (Eqs. (24)-(25), App. B): Tr(A rho_n) after every slice in the
+  // forward sweep, Phi -= beta dt sum_n, and lambda -= beta dt A at every
+  // slice boundary of the backward sweep (the combined adjoint).
+  og_status penalty_trace(int n) {
+    if (ctx->pen_beta == 0.0 || !ctx->pen_coo) return OG_OK;
+    og::penalty_trace_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(ctx->pen_coo, ctx->pen_nnz, cur_hi, cur_lo, E, d,
+                                                                   pen + n, (long)n_t + 1);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+  og_status penalty_inject() {
+    if (ctx->pen_beta == 0.0 || !ctx->pen_coo) return OG_OK;
+    const unsigned gx = (unsigned)std::max(1, std::min((ctx->pen_nnz + 255) / 256, 64));
+    og::inject_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(ctx->pen_coo, ctx->pen_nnz, -ctx->pen_beta * dt,
+                                                                lam_hi, E, d);
+    OG_CHECK_LAUNCH();
+    return OG_OK;
+  }
+
   og_status cost(const void* sigma, double* phi, hipStream_t s) override {
     og::cost_kernel<T><<<dim3((unsigned)B), 256, 0, s>>>(static_cast<const double*>(sigma), cur_hi, cur_lo, E, d, phi);
     OG_CHECK_LAUNCH();
+    if (ctx->pen_beta != 0.0 && ctx->pen_coo) {
+      og::penalty_sum_kernel<<<dim3((unsigned)B), 256, 0, s>>>(pen, (long)n_t + 1, ctx->pen_beta * dt, phi);
+      OG_CHECK_LAUNCH();
+    }
     return OG_OK;
   }
 
@@ -765,6 +798,7 @@ struct Engine : EngineBase {
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dt / nsub);
     OG_TRY(load(sigma, 0, lam_hi, lam_lo));
+    OG_TRY(penalty_inject());
     for (int seg = n_seg - 1; seg >= 0; --seg) {
       const int j0 = seg * S, j1 = std::min(n_t, j0 + S), n = j1 - j0;
       OG_TRY(copy_state(slot(sg_hi, 0), slot(sg_lo, 0), slot(ck_hi, seg), slot(ck_lo, seg)));
@@ -778,6 +812,7 @@ struct Engine : EngineBase {
           const double cf[1] = {dt};
           OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
           OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
+          OG_TRY(penalty_inject());
           continue;
         }
         // exact derivative of the RK4-discretised Phi: reverse through the
@@ -810,8 +845,18 @@ struct Engine : EngineBase {
           OG_TRY(contract(j, 4, Xs, Ls, cf, sub != nsub - 1));
           OG_TRY(stage(ADJ, og::SM_FINAL, j, Zb1, lam_hi, lam_lo, lam_hi, lam_lo, h / T(4), Zb1, Zb2, Zb3));
         }
+        OG_TRY(penalty_inject());
       }
     }
+    return OG_OK;
+  }
+
+  og_status gradient_sum(double* out, int accumulate, hipStream_t s) override {
+    if (K == 0) return OG_OK;
+    const long n = (long)n_t * K;
+    og::reduce_partials_sum_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, s>>>(grad, B, n_t, K, accumulate,
+                                                                                    out);
+    OG_CHECK_LAUNCH();
     return OG_OK;
   }
 
@@ -1274,6 +1319,7 @@ og_status og_destroy(og_ctx* ctx) {
   for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
   if (ctx->status_dev) (void)hipFree(ctx->status_dev);
   if (ctx->umax_dev) (void)hipFree(ctx->umax_dev);
+  if (ctx->pen_coo) (void)hipFree(ctx->pen_coo);
   delete ctx;
   return OG_OK;
 }
@@ -1379,12 +1425,90 @@ og_status og_gradient(og_ctx* ctx, double* grad, void* stream) {
   return OG_OK;
 }
 
+og_status og_gradient_sum(og_ctx* ctx, double* grad, int accumulate, void* stream) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (!grad) return fail(OG_ERR_ARG, "grad is NULL");
+  if (ctx->phase < 2) return fail(OG_ERR_ORDER, "og_gradient_sum before og_adjoint");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  OG_TRY(ctx->eng->gradient_sum(grad, accumulate ? 1 : 0, st));
+  if (ctx->opt.validate) {
+    int flag = 0;
+    OG_HIP(hipMemcpyAsync(&flag, ctx->status_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    OG_HIP(hipStreamSynchronize(st));
+    if (flag) return fail(OG_ERR_NONFINITE, "a propagated state became non-finite");
+  }
+  return OG_OK;
+}
+
+og_status og_set_penalty(og_ctx* ctx, const void* A, double beta) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (!std::isfinite(beta)) return fail(OG_ERR_ARG, "beta must be finite");
+  if (ctx->pen_coo) {
+    (void)hipFree(ctx->pen_coo);
+    ctx->pen_coo = nullptr;
+    ctx->pen_nnz = 0;
+  }
+  ctx->pen_beta = 0.0;
+  if (beta == 0.0 || !A) return OG_OK;
+  const int d = ctx->d;
+  Mat a = from_ptr(A, d, 0);
+  for (auto& z : a.a)
+    if (!std::isfinite(z.real()) || !std::isfinite(z.imag())) return fail(OG_ERR_ARG, "non-finite entry of A");
+  if (ctx->opt.validate && herm_defect(a) > 1e-12) return fail(OG_ERR_NOT_HERMITIAN, "A is not Hermitian");
+  // entries of the upper triangle and their conjugate mirror: exactly Hermitian
+  std::vector<og::CooEntry> coo;
+  for (int i = 0; i < d; ++i)
+    for (int j = i; j < d; ++j) {
+      const cd v = a(i, j);
+      if (v == cd(0, 0)) continue;
+      if (i == j) {
+        coo.push_back(og::CooEntry{i, i, v.real(), 0.0});
+      } else {
+        coo.push_back(og::CooEntry{i, j, v.real(), v.imag()});
+        coo.push_back(og::CooEntry{j, i, v.real(), -v.imag()});
+      }
+    }
+  if (coo.empty()) return OG_OK;
+  OG_HIP(hipMalloc((void**)&ctx->pen_coo, coo.size() * sizeof(og::CooEntry)));
+  OG_HIP(hipMemcpy(ctx->pen_coo, coo.data(), coo.size() * sizeof(og::CooEntry), hipMemcpyHostToDevice));
+  ctx->pen_nnz = (int)coo.size();
+  ctx->pen_beta = beta;
+  return OG_OK;
+}
+
+og_status og_filter_apply(int B, int N, int M, int K, double dtu, double dts, double omega0, const double* u,
+                          double* s, void* stream) {
+  g_err.clear();
+  if (B < 1 || N < 1 || M < 1 || K < 1 || K > og::MAXK) return fail(OG_ERR_ARG, "bad sizes");
+  if (!(dtu > 0) || !(dts > 0) || !(omega0 > 0) || !std::isfinite(omega0)) return fail(OG_ERR_ARG, "bad grid");
+  if (!u || !s) return fail(OG_ERR_ARG, "NULL pointer");
+  og::filter_apply_kernel<<<dim3((unsigned)((M + 255) / 256), (unsigned)B), 256, 0,
+                            static_cast<hipStream_t>(stream)>>>(N, M, K, dtu, dts, omega0, u, s);
+  OG_CHECK_LAUNCH();
+  return OG_OK;
+}
+
+og_status og_filter_grad(int B, int N, int M, int K, double dtu, double dts, double omega0, int fix_ends,
+                         const double* g_s, double* g_u, void* stream) {
+  g_err.clear();
+  if (B < 1 || N < 1 || M < 1 || K < 1 || K > og::MAXK) return fail(OG_ERR_ARG, "bad sizes");
+  if (!(dtu > 0) || !(dts > 0) || !(omega0 > 0) || !std::isfinite(omega0)) return fail(OG_ERR_ARG, "bad grid");
+  if (!g_s || !g_u) return fail(OG_ERR_ARG, "NULL pointer");
+  og::filter_grad_kernel<<<dim3((unsigned)((N + 255) / 256), (unsigned)B), 256, 0,
+                           static_cast<hipStream_t>(stream)>>>(N, M, K, dtu, dts, omega0, fix_ends, g_s, g_u);
+  OG_CHECK_LAUNCH();
+  return OG_OK;
+}
+
 og_status og_server_create(og_server** out, og_ctx* ctx, int max_active) {
   g_err.clear();
   if (!out || !ctx || !ctx->eng) return fail(OG_ERR_ARG, "NULL argument");
   *out = nullptr;
   if (max_active < 1 || max_active > 65536) return fail(OG_ERR_ARG, "max_active must be in [1, 65536]");
   if (ctx->path != OG_PATH_BANDED) return fail(OG_ERR_SHAPE, "serving needs the banded path");
+  if (ctx->pen_beta != 0.0) return fail(OG_ERR_ARG, "serving does not support the penalty");
   ctx->eng->serve_clear();
   og_server* s = new og_server();
   s->ctx = ctx;

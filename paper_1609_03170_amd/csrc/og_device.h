@@ -976,6 +976,123 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* __re
   grad[idx] = s;
 }
 
+// Multi-state index (sum over the batch): grad[j, k] (+)= sum_b sum_ch
+// part[b, j, ch, k], batch-major in a fixed order.
+__global__ __launch_bounds__(256) void reduce_partials_sum_kernel(const double* __restrict__ part, int B, long n_t,
+                                                                  int K, int accumulate, double* __restrict__ grad) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_t * K) return;
+  const long j = idx / K;
+  const int k = (int)(idx - j * K);
+  double s = 0.0;
+  for (int b = 0; b < B; ++b) {
+    double sb = 0.0;
+    for (int ch = 0; ch < NCH; ++ch) sb += part[(((long)b * n_t + j) * NCH + ch) * K + k];
+    s += sb;
+  }
+  grad[idx] = accumulate ? grad[idx] + s : s;
+}
+
+// ---------------------------------------------------------------------------
+// Photon-number (or any observable) penalty, Eqs. (24)-(25): A is given as
+// a list of its nonzero entries (both triangles, exactly Hermitian).
+// ---------------------------------------------------------------------------
+struct CooEntry {
+  int i, j;
+  double re, im;
+};
+
+// pen[b * stride] = Re Tr(A rho_b) = sum Re(A_ij conj(rho_ij)), rho = hi + lo.
+template <typename T>
+__global__ __launch_bounds__(256) void penalty_trace_kernel(const CooEntry* __restrict__ A, int nnz,
+                                                            const cpx<T>* __restrict__ hi,
+                                                            const cpx<T>* __restrict__ lo, long s_s, int d,
+                                                            double* __restrict__ pen, long pen_s) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < nnz; e += 256) {
+    const CooEntry a = A[e];
+    const long idx = (long)a.i * d + a.j;
+    const cpx<T> h = hi[(long)b * s_s + idx];
+    double rr = h.re, ri = h.im;
+    if (lo) {
+      const cpx<T> l = lo_at(lo + (long)b * s_s, d, idx);
+      rr += (double)l.re;
+      ri += (double)l.im;
+    }
+    acc += a.re * rr + a.im * ri;
+  }
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) pen[(long)b * pen_s] = s;
+}
+
+// lambda_b += scale * A (all entries of both triangles: stays exactly Hermitian).
+template <typename T>
+__global__ __launch_bounds__(256) void inject_kernel(const CooEntry* __restrict__ A, int nnz, double scale,
+                                                     cpx<T>* __restrict__ lam, long s_s, int d) {
+  const int b = blockIdx.y;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < nnz; e += gridDim.x * 256) {
+    const CooEntry a = A[e];
+    cpx<T>* p = lam + (long)b * s_s + (long)a.i * d + a.j;
+    cpx<T> v = *p;
+    v.re += (T)(scale * a.re);
+    v.im += (T)(scale * a.im);
+    *p = v;
+  }
+}
+
+// phi[b] -= beta * dt * sum_n pen[b][n] (fixed order).
+__global__ __launch_bounds__(256) void penalty_sum_kernel(const double* __restrict__ pen, long n_pts, double w,
+                                                          double* __restrict__ phi) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (long n = threadIdx.x; n < n_pts; n += 256) acc += pen[(long)b * n_pts + n];
+  const double s = block_sum256(acc, sh);
+  if (threadIdx.x == 0) phi[b] -= w * s;
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian control filter, App. A: T[n][j] (0-based) =
+//   (erf(w0 (n dts - j dtu) / 2) - erf(w0 (n dts - (j+1) dtu) / 2)) / 2,
+// s[b][n][k] = sum_j T[n][j] u[b][j][k];  g_u[b][j][k] = sum_n T[n][j] g_s[b][n][k].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double filter_T(int n, int j, double dtu, double dts, double w0) {
+  const double t = n * dts;
+  return 0.5 * (erf(0.5 * w0 * (t - j * dtu)) - erf(0.5 * w0 * (t - (j + 1) * dtu)));
+}
+
+__global__ __launch_bounds__(256) void filter_apply_kernel(int N, int M, int K, double dtu, double dts, double w0,
+                                                           const double* __restrict__ u, double* __restrict__ s) {
+  const int b = blockIdx.y;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= M) return;
+  double acc[MAXK];
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const double t = filter_T(n, j, dtu, dts, w0);
+    for (int k = 0; k < K; ++k) acc[k] += t * u[((long)b * N + j) * K + k];
+  }
+  for (int k = 0; k < K; ++k) s[((long)b * M + n) * K + k] = acc[k];
+}
+
+__global__ __launch_bounds__(256) void filter_grad_kernel(int N, int M, int K, double dtu, double dts, double w0,
+                                                          int fix_ends, const double* __restrict__ gs,
+                                                          double* __restrict__ gu) {
+  const int b = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  double acc[MAXK];
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  if (!(fix_ends && (j == 0 || j == N - 1)))
+    for (int n = 0; n < M; ++n) {
+      const double t = filter_T(n, j, dtu, dts, w0);
+      for (int k = 0; k < K; ++k) acc[k] += t * gs[((long)b * M + n) * K + k];
+    }
+  for (int k = 0; k < K; ++k) gu[((long)b * N + j) * K + k] = acc[k];
+}
+
 // ---------------------------------------------------------------------------
 // Precision conversions.  hi = fl_T(x), lo = fl_T(x - hi).
 // ---------------------------------------------------------------------------
