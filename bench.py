@@ -42,15 +42,17 @@ def _parse():
     ap.add_argument("--path", default="banded", choices=["banded", "dense", "auto"])
     ap.add_argument("--precisions", default="f32,f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices", type=int, default=60, help="slices of the CPU oracle sample")
+    ap.add_argument("--cpu-slices", type=int, default=600, help="slices of the CPU oracle sample")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary lines (exact gradient, small batches, dense path)")
     ap.add_argument("--profile-every", type=int, default=97)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes 5 times (for scaling HBM counters)")
-    ap.add_argument("--serve-requests", type=int, default=384,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving leg at the offered load (0 = no serving leg)")
     ap.add_argument("--serve-saturation", type=int, default=192,
                     help="requests submitted at once to measure the saturation throughput")
-    ap.add_argument("--serve-loads", default="0.8", help="offered loads as fractions of saturation")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95", help="offered loads as fractions of saturation")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
@@ -118,10 +120,49 @@ def serving_leg(args):
         _log(f"[serve] offered load {load:.2f} x saturation = {rate:.2f} req/s, {n_load} requests")
         stream = [dict(r, arrival=r["arrival"] - t_first) for r in tail]
         res = loop.run(stream, wl.serving_controls, time_scale=1.0 / rate, log=_log)
+        # algorithmic HBM bytes of the banded model (18 d^2 float32 complex
+        # elements per slice) over the wall time of the run
+        work = sum(18.0 * (r["shape"][0] * r["shape"][1]) ** 2 * 8 * r["n_t"] for r in stream)
+        wall = res.wall
         out["loads"].append({"offered_load": load, "offered_req_per_s": rate, "requests": n_load,
                              "throughput_req_per_s": res.throughput(), "p50_ms": 1000 * res.percentile(50),
-                             "p99_ms": 1000 * res.percentile(99), "peak_hbm_gib": res.peak_bytes / 2**30})
+                             "p99_ms": 1000 * res.percentile(99), "peak_hbm_gib": res.peak_bytes / 2**30,
+                             "hbm_frac": work / wall / (HBM_PEAK_GBS * 1e9)})
     loop.close()
+    return out
+
+
+def _brief(r, w, golden_err=True):
+    keys = ("prec", "batch", "path", "gradient", "steps", "value", "ms_per_step", "kern_us")
+    out = {k: r[k] for k in keys if k in r}
+    out["ms_per_grad_eval"] = r["ms_per_step"] / r["batch"]
+    if golden_err and "err_phi" in r:
+        out["err_vs_oracle"] = {"phi": r["err_phi"], "grad": r["err_grad"], "problem": 0}
+    return out
+
+
+def extras_leg(args, w, golden):
+    """Secondary lines on the same workload, one timed evaluation each: the
+    exact (reverse-mode RK4) gradient at the headline batch; single-problem
+    latency (B = 1) in both precisions and B = 16; the dense matrix-core path
+    (complex GEMMs, B = 4) in both precisions, with the MFMA roofline of its
+    first GEMM of every stage (B (1 + J) products of 8 d^3 real flops)."""
+    out = {}
+    r = run_gpu(args, "f32", w, golden, steps=1, warmup=0, gmode="exact")
+    out["exact_f32"] = _brief(r, w)
+    for prec, B in (("f32", 1), ("f64", 1), ("f32", 16)):
+        r = run_gpu(args, prec, w, golden, batch=B, steps=1, warmup=0)
+        out[f"b{B}_{prec}"] = _brief(r, w)
+    for prec in ("f32", "f64"):
+        B = 4
+        r = run_gpu(args, prec, w, golden, batch=B, steps=1, warmup=0, path="dense")
+        b = _brief(r, w)
+        flops = B * (1 + w.J) * 8.0 * w.d ** 3
+        tf = flops / (r["kern_us"] * 1e-6) / 1e12 if r["kern_us"] > 0 else None
+        b["roofline"] = {"bound": "mfma", "kernel": "zgemm_kernel (first GEMM of each stage)", "achieved": tf,
+                         "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                         "frac": tf / PEAK_TFLOPS[prec] if tf else None}
+        out[f"dense_{prec}"] = b
     return out
 
 
@@ -141,15 +182,23 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(args, prec, w, golden):
+def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=None, gmode=None):
+    """Time `steps` gradient evaluations of the first `batch` problems of w
+    (after `warmup` untimed ones); defaults from the command line."""
     import torch
 
     from paper_1609_03170_amd import Problem
 
     dev = torch.device("cuda", 0)
-    B, n_t = args.batch, args.n_t
-    p = Problem.from_workload(w, prec=prec, path=args.path, gmode=args.gmode)
-    u = torch.tensor(np.ascontiguousarray(w.u.reshape(B, n_t, w.K)), device=dev)
+    B = args.batch if batch is None else batch
+    n_t = args.n_t
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    path = args.path if path is None else path
+    gmode = args.gmode if gmode is None else gmode
+    p = Problem.from_workload(w, prec=prec, path=path, gmode=gmode)
+    u_all = w.u.reshape(-1, n_t, w.K)
+    u = torch.tensor(np.ascontiguousarray(u_all[:B]), device=dev)
     rho0 = torch.tensor(np.broadcast_to(w.rho0, (B, w.d, w.d)).copy(), device=dev)
     sigma = torch.tensor(w.sigma, device=dev)
     ws = torch.empty(p.workspace_bytes(B, n_t), dtype=torch.uint8, device=dev)
@@ -159,26 +208,26 @@ def run_gpu(args, prec, w, golden):
         phi, g = p.cost_and_grad(u, rho0, sigma, w.dt, workspace=ws)
         return phi, g
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step()
         torch.cuda.synchronize()
-        _log(f"[bench] {prec} warmup {i + 1}/{args.warmup} done")
+        _log(f"[bench] {prec} warmup {i + 1}/{warmup} done")
     torch.cuda.synchronize()
     p.profile(args.profile_every)
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         phi, g = step()
         torch.cuda.synchronize()
-        _log(f"[bench] {prec} step {i + 1}/{args.steps} done ({time.perf_counter() - t0:.2f} s)")
+        _log(f"[bench] {prec} B={B} {path} {gmode} step {i + 1}/{steps} done ({time.perf_counter() - t0:.2f} s)")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_us, kern_n = p.profile_read()
     p.profile(0)
     phi = phi.cpu().numpy()
     g = g.cpu().numpy()
-    out = dict(prec=prec, elapsed=elapsed, ms_per_step=1000 * elapsed / args.steps,
-               value=B * args.steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path)
-    gkey = "g_grape1" if args.gmode == "grape1" else "g_exact"
+    out = dict(prec=prec, batch=B, steps=steps, elapsed=elapsed, ms_per_step=1000 * elapsed / steps,
+               value=B * steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path, gradient=gmode)
+    gkey = "g_grape1" if gmode == "grape1" else "g_exact"
     if golden is not None and golden[gkey].shape[0] == n_t:
         out["err_phi"] = float(abs(phi[0] - golden["phi"]) / abs(golden["phi"]))
         out["err_grad"] = float(np.linalg.norm(g[0] - golden[gkey]) / np.linalg.norm(golden[gkey]))
@@ -214,16 +263,11 @@ def measured_traffic(prec, batch, path):
         return None
 
 
-def cpu_baseline(args, w):
-    """The float64 oracle on the host cores, on a bounded sample: the first
-    args.cpu_slices slices of problem 0 (forward + backward + first-order
-    gradient), scaled to one full gradient evaluation."""
+def _oracle_sample(w, u, n_t):
     import resource
 
     from oracle import rk
 
-    n = args.cpu_slices
-    u = w.u.reshape(args.batch, args.n_t, w.K)[0, :n]
     m = rk.Model.from_workload(w, sparse=True)
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
@@ -233,11 +277,46 @@ def cpu_baseline(args, w):
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return wall, cpu
+
+
+def _host():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "numpy": np.__version__}
+
+
+def cpu_baseline(args, w):
+    """The float64 oracle on the host cores, on a bounded sample: the first
+    args.cpu_slices slices of problem 0 (forward + backward + first-order
+    gradient), scaled to one full gradient evaluation; then a shorter sample
+    with every thread pool limited to one thread."""
+    n = args.cpu_slices
+    u = w.u.reshape(-1, args.n_t, w.K)[0]
+    wall, cpu = _oracle_sample(w, u[:n], args.n_t)
     per_eval = wall * args.n_t / n
-    return {"value": 1.0 / per_eval, "unit": "grad-evals/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
-            "sample": f"float64 NumPy/SciPy-sparse oracle, problem 0, first {n} of {args.n_t} slices "
-                      f"(forward + backward + Eq. (13) gradient) in {wall:.1f} s, scaled x{args.n_t / n:.0f}"}
+    out = {"value": 1.0 / per_eval, "unit": "grad-evals/s", "cores": max(1, int(round(cpu / wall))),
+           "kind": "oracle",
+           "sample": f"float64 NumPy/SciPy-sparse oracle, problem 0, first {n} of {args.n_t} slices "
+                     f"(forward + backward + Eq. (13) gradient) in {wall:.1f} s, scaled x{args.n_t / n:.0f}",
+           "host": _host()}
+    try:
+        from threadpoolctl import threadpool_limits
+
+        n1 = max(1, n // 3)
+        with threadpool_limits(limits=1):
+            wall1, _ = _oracle_sample(w, u[:n1], args.n_t)
+        out["one_thread_value"] = n1 / (wall1 * args.n_t)
+        out["one_thread_sample"] = f"first {n1} slices in {wall1:.1f} s"
+    except ImportError:
+        pass
+    return out
 
 
 def main():
@@ -288,7 +367,7 @@ def main():
             "batch": args.batch, "n_t": args.n_t, "path": head["path"], "gradient": args.gmode,
             "ckpt_stride": int(math.ceil(math.sqrt(args.n_t))), "parallelism": "none (1 GPU)",
         },
-        "rk_steps_per_s": head["value"] * args.n_t * 3,
+        "rk_steps_per_s": head["value"] * args.n_t * 2,
         "roofline": {
             "bound": "hbm",
             "kernel": "band_stage_kernel" if head["path"] == "banded" else "zgemm_kernel",
@@ -303,6 +382,13 @@ def main():
             "algorithmic_bytes_per_launch": per_launch,
         },
     }
+    # whole path: per slice the forward and adjoint sweeps each run 4 stages
+    # that read and write one state, and the gradient reads rho and lambda
+    # (18 d^2 elements per slice; the checkpoint recompute is not counted)
+    path_bytes = 18.0 * d * d * elem * args.n_t
+    line["path_roofline"] = {"algorithmic_bytes_per_grad_eval": path_bytes,
+                             "achieved": head["value"] * path_bytes / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": head["value"] * path_bytes / 1e9 / HBM_PEAK_GBS}
     if "err_phi" in head:
         line["err_vs_oracle"] = {"phi": head["err_phi"], "grad": head["err_grad"], "problem": 0}
     if "f64" in results and "f32" in results:
@@ -310,6 +396,8 @@ def main():
         line["fp64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                         "err_vs_oracle": {"phi": f64.get("err_phi"), "grad": f64.get("err_grad")}}
         line["speedup_fp32_over_fp64"] = head["value"] / f64["value"]
+    if not args.no_extras:
+        line["extras"] = extras_leg(args, w, golden)
     if args.serve_requests > 0:
         line["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
