@@ -826,7 +826,7 @@ __global__ __launch_bounds__(256) void cost_kernel(const double* __restrict__ si
 // reduce_partials_kernel sums in a fixed order.  Products are formed in T;
 // each lane sums at most ceil(d / 64) * nH of them in T before adding to a
 // float64 accumulator.
-constexpr int NCH = 4;
+constexpr int NCH = 16;  // row chunks (blocks) per problem of a contraction
 
 template <typename T>
 struct PairArgs {
@@ -865,23 +865,29 @@ __device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, cons
                                               const HBand<T>& hb, int K, int d, int a0, int a1, double* acc) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nH = hb.nH, dm = d - 1;
+  // CG column chunks of 64 per pass: their loads are all issued before the
+  // products (diagonals beyond nH have offset 0 and are loaded but unused)
+  constexpr int CG = 4;
   for (int a = a0 + wave; a < a1; a += 4) {
     // this lane's part of the row products P_t = sum_c X[a + o_t, c] conj(L[a, c])
     cpx<T> P[NH];
 #pragma unroll
     for (int t = 0; t < NH; ++t) P[t] = mkc<T>(0, 0);
-    for (int c0 = 0; c0 < d; c0 += 64) {
-      const int c = c0 + lane;
-      const int cc = min(c, dm);
-      cpx<T> l = ldm(Lm, __umul24(a, d) + cc);
-      if (c > dm) l = mkc<T>(0, 0);
-      cpx<T> x[NH];
+    for (int c0 = 0; c0 < d; c0 += 64 * CG) {
+      cpx<T> l[CG], x[CG][NH];
 #pragma unroll
-      for (int t = 0; t < NH; ++t)
-        if (t < nH) x[t] = ldm(X, __umul24(clampi(a + hb.offH[t], dm), d) + cc);
+      for (int g = 0; g < CG; ++g) {
+        const int c = c0 + 64 * g + lane;
+        const int cc = min(c, dm);
+        l[g] = ldm(Lm, __umul24(a, d) + cc);
+        if (c > dm) l[g] = mkc<T>(0, 0);
 #pragma unroll
-      for (int t = 0; t < NH; ++t)
-        if (t < nH) cfmac(P[t], x[t], l);
+        for (int t = 0; t < NH; ++t) x[g][t] = ldm(X, __umul24(clampi(a + hb.offH[t], dm), d) + cc);
+      }
+#pragma unroll
+      for (int g = 0; g < CG; ++g)
+#pragma unroll
+        for (int t = 0; t < NH; ++t) cfmac(P[t], x[g][t], l[g]);
     }
     // weight by H_k[a, a + o_t] once per row
     for (int k = 0; k < K; ++k) {
