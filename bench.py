@@ -144,13 +144,18 @@ def _brief(r, w, golden_err=True):
 def extras_leg(args, w, golden):
     """Secondary lines on the same workload, one timed evaluation each: the
     exact (reverse-mode RK4) gradient at the headline batch; single-problem
-    latency (B = 1) in both precisions and B = 16; the dense matrix-core path
+    latency (B = 1) in both precisions and the batch sweep B = 4, 16, 64, 256;
+    the dense matrix-core path
     (complex GEMMs, B = 4) in both precisions, with the MFMA roofline of its
     first GEMM of every stage (B (1 + J) products of 8 d^3 real flops)."""
+    import workloads as wl
+
     out = {}
     r = run_gpu(args, "f32", w, golden, steps=1, warmup=0, gmode="exact")
     out["exact_f32"] = _brief(r, w)
-    for prec, B in (("f32", 1), ("f64", 1), ("f32", 16)):
+    for prec, B in (("f32", 1), ("f64", 1), ("f32", 4), ("f32", 16), ("f32", 64), ("f32", 256)):
+        if B > w.u.reshape(-1, args.n_t, w.K).shape[0]:
+            w = wl.config_c3(batch=B, n_t=args.n_t)
         r = run_gpu(args, prec, w, golden, batch=B, steps=1, warmup=0)
         out[f"b{B}_{prec}"] = _brief(r, w)
     for prec in ("f32", "f64"):
@@ -316,7 +321,31 @@ def cpu_baseline(args, w):
         out["one_thread_sample"] = f"first {n1} slices in {wall1:.1f} s"
     except ImportError:
         pass
+    out["other_configs"] = cpu_other_configs()
     return out
+
+
+def cpu_other_configs():
+    """The oracle's time per gradient evaluation at the other configurations
+    (dense operators): C1 in full, C2 and the dense d = 512 case on their
+    first slices, scaled to the full N_t."""
+    import workloads as wl
+
+    res = {}
+    for name, w, n in (("C1 d=10 N_t=200", wl.config_c1(), 200), ("C2 d=90 N_t=2000", wl.config_c2(), 100),
+                       ("C4 d=512 N_t=1000", wl.config_c4(), 3)):
+        from oracle import rk
+
+        u = w.u.reshape(-1, w.u.shape[-2], w.K)[0]
+        n_t = u.shape[0]
+        m = rk.Model.from_workload(w, sparse=False)
+        t0 = time.perf_counter()
+        rhos = rk.forward(m, u[:n], w.rho0, w.dt)
+        lams = rk.backward(m, u[:n], w.sigma, w.dt)
+        rk.gradient_grape1(m, u[:n], rhos, lams, w.dt)
+        wall = time.perf_counter() - t0
+        res[name] = {"s_per_grad_eval": wall * n_t / n, "sample_slices": n}
+    return res
 
 
 def main():

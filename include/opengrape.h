@@ -126,6 +126,25 @@ og_status og_create(og_ctx **out, int d, int K, int J,
                     const void *H0, const void *Hk, const void *c_ops,
                     const double *gamma, const og_options *opt);
 
+/*
+ * As og_create, with every operator given in diagonal storage on one shared
+ * offset list (the structure of ladder operators of coupled modes, Sec. IV):
+ *   n_diag         number of diagonals, 1 <= n_diag <= 2 d - 1.
+ *   offsets        host, n_diag distinct ints in (-d, d); diagonal t holds
+ *                  the entries (i, i + offsets[t]).
+ *   H0_diags       host, complex128 n_diag x d: H0_diags[t][i] = H0[i, i + offsets[t]].
+ *   Hk_diags       host, complex128 K x n_diag x d (NULL if K = 0).
+ *   c_diags        host, complex128 J x n_diag x d (NULL if J = 0).
+ *   gamma, opt     as og_create.
+ * Entries whose column i + offsets[t] falls outside [0, d) are ignored.
+ * The operators are expanded on the host and the context is created as by
+ * og_create (same validation, path choice and errors); repeated offsets
+ * return OG_ERR_ARG.
+ */
+og_status og_create_banded(og_ctx **out, int d, int K, int J, int n_diag, const int *offsets,
+                           const void *H0_diags, const void *Hk_diags, const void *c_diags,
+                           const double *gamma, const og_options *opt);
+
 /* Free the context and its device memory (synchronizes the device). */
 og_status og_destroy(og_ctx *ctx);
 

@@ -39,7 +39,7 @@ EXPORTS = (
     "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_profile", "og_profile_read",
     "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
     "og_server_destroy", "og_status_string", "og_last_error", "og_gradient_sum", "og_set_penalty",
-    "og_filter_apply", "og_filter_grad",
+    "og_filter_apply", "og_filter_grad", "og_create_banded",
 )
 
 
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH):
     lib.og_default_options.restype = None
     lib.og_create.argtypes = [ctypes.POINTER(vp), i, i, i, vp, vp, vp, vp, ctypes.POINTER(OgOptions)]
     lib.og_create.restype = i
+    lib.og_create_banded.argtypes = [ctypes.POINTER(vp), i, i, i, i, vp, vp, vp, vp, vp, ctypes.POINTER(OgOptions)]
+    lib.og_create_banded.restype = i
     lib.og_destroy.argtypes = [vp]
     lib.og_destroy.restype = i
     lib.og_path_used.argtypes = [vp]
@@ -148,12 +150,15 @@ class Problem:
     states complex128 [B, d, d]."""
 
     def __init__(self, H0, Hk, c_ops, gammas, *, prec="f64", gmode="grape1", path="auto", n_sub=1,
-                 ckpt_stride=0, validate=True, device=None):
+                 ckpt_stride=0, validate=True, device=None, _banded=None):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("opengrape needs a ROCm GPU; no device is visible")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
+        if _banded is not None:
+            self._init_banded(lib, _banded, gammas, prec, gmode, path, n_sub, ckpt_stride, validate)
+            return
         H0 = np.asarray(H0)
         d = H0.shape[0]
         Hk = np.asarray(Hk, dtype=np.complex128).reshape(-1, d, d) if len(Hk) else np.zeros((0, d, d), np.complex128)
@@ -184,6 +189,42 @@ class Problem:
     @classmethod
     def from_workload(cls, w, **kw):
         return cls(w.H0, w.Hk, w.c_ops, w.gammas, **kw)
+
+    @classmethod
+    def from_banded(cls, offsets, H0_diags, Hk_diags, c_diags, gammas, **kw):
+        """Operators in diagonal storage on one offset list (og_create_banded):
+        H0_diags [n_diag, d], Hk_diags [K, n_diag, d], c_diags [J, n_diag, d],
+        entry [t, i] = operator[i, i + offsets[t]]."""
+        return cls(None, None, None, gammas, _banded=(offsets, H0_diags, Hk_diags, c_diags), **kw)
+
+    def _init_banded(self, lib, banded, gammas, prec, gmode, path, n_sub, ckpt_stride, validate):
+        offsets, H0d, Hkd, cd = banded
+        self._offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1))
+        n_diag = self._offs.shape[0]
+        self._h0 = np.ascontiguousarray(np.asarray(H0d, dtype=np.complex128))
+        if self._h0.ndim != 2 or self._h0.shape[0] != n_diag:
+            raise ValueError("H0_diags must be [n_diag, d]")
+        d = self._h0.shape[1]
+        self._hk = np.ascontiguousarray(np.asarray(Hkd, dtype=np.complex128).reshape(-1, n_diag, d))
+        self._c = np.ascontiguousarray(np.asarray(cd, dtype=np.complex128).reshape(-1, n_diag, d))
+        self.d, self.K, self.J = d, self._hk.shape[0], self._c.shape[0]
+        self._g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).reshape(-1))
+        if self._g.shape[0] != self.J:
+            raise ValueError("one rate per collapse operator")
+        opt = OgOptions()
+        lib.og_default_options(ctypes.byref(opt))
+        opt.prec, opt.gmode, opt.path = PREC[prec], GMODE[gmode], PATH[path]
+        opt.n_sub, opt.ckpt_stride, opt.validate = int(n_sub), int(ckpt_stride), int(bool(validate))
+        self.prec, self.gmode, self.n_sub = prec, gmode, int(n_sub)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.og_create_banded(ctypes.byref(ctx), d, self.K, self.J, n_diag, self._offs.ctypes.data,
+                                        self._h0.ctypes.data, self._hk.ctypes.data if self.K else None,
+                                        self._c.ctypes.data if self.J else None,
+                                        self._g.ctypes.data if self.J else None, ctypes.byref(opt)))
+        self._ctx = ctx
+        self._lib = lib
+        self._keep = {}
 
     @property
     def path(self) -> str:

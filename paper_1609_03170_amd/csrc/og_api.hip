@@ -1312,6 +1312,44 @@ og_status og_create(og_ctx** out, int d, int K, int J, const void* H0p, const vo
   return OG_OK;
 }
 
+og_status og_create_banded(og_ctx** out, int d, int K, int J, int n_diag, const int* offsets, const void* H0d,
+                           const void* Hkd, const void* cd_, const double* gamma, const og_options* opt) {
+  g_err.clear();
+  if (!out) return fail(OG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > 4096) return fail(OG_ERR_ARG, "d must be in [1, 4096]");
+  if (K < 0 || K > og::MAXK) return fail(OG_ERR_ARG, "K must be in [0, 16]");
+  if (J < 0 || J > 16) return fail(OG_ERR_ARG, "J must be in [0, 16]");
+  if (n_diag < 1 || n_diag > 2 * d - 1) return fail(OG_ERR_ARG, "n_diag must be in [1, 2 d - 1]");
+  if (!offsets || !H0d) return fail(OG_ERR_ARG, "offsets or H0_diags is NULL");
+  if (K > 0 && !Hkd) return fail(OG_ERR_ARG, "Hk_diags is NULL with K > 0");
+  if (J > 0 && !cd_) return fail(OG_ERR_ARG, "c_diags is NULL with J > 0");
+  std::vector<int> seen;
+  for (int t = 0; t < n_diag; ++t) {
+    const int o = offsets[t];
+    if (o <= -d || o >= d) return fail(OG_ERR_ARG, "offset outside (-d, d)");
+    if (std::find(seen.begin(), seen.end(), o) != seen.end()) return fail(OG_ERR_ARG, "repeated offset");
+    seen.push_back(o);
+  }
+  // expand operator m of an array of n_ops diagonal sets into dense row-major d x d
+  const size_t E = (size_t)d * d;
+  auto expand = [&](const void* src, int n_ops, std::vector<cd>& dst) {
+    const cd* v = static_cast<const cd*>(src);
+    dst.assign((size_t)n_ops * E, cd(0, 0));
+    for (int m = 0; m < n_ops; ++m)
+      for (int t = 0; t < n_diag; ++t) {
+        const int o = offsets[t];
+        const cd* row = v + ((size_t)m * n_diag + t) * d;
+        for (int i = std::max(0, -o); i < d && i + o < d; ++i) dst[(size_t)m * E + (size_t)i * d + i + o] = row[i];
+      }
+  };
+  std::vector<cd> h0, hk, cc;
+  expand(H0d, 1, h0);
+  if (K > 0) expand(Hkd, K, hk);
+  if (J > 0) expand(cd_, J, cc);
+  return og_create(out, d, K, J, h0.data(), K > 0 ? hk.data() : nullptr, J > 0 ? cc.data() : nullptr, gamma, opt);
+}
+
 og_status og_destroy(og_ctx* ctx) {
   if (!ctx) return OG_OK;
   (void)hipDeviceSynchronize();

@@ -82,6 +82,34 @@ def test_host_argument_errors_without_gpu():
     assert lib.og_destroy(None) == 0
 
 
+def test_create_banded_argument_errors_without_gpu():
+    api, lib = _lib()
+    d = 4
+    offs = np.array([0, 1, -1], dtype=np.int32)
+    H0d = np.zeros((3, d), np.complex128)
+    H0d[0] = np.arange(d)
+
+    def create(n_diag, offsets, h0, K=0, hk=None):
+        ctx = ctypes.c_void_p()
+        return lib.og_create_banded(ctypes.byref(ctx), d, K, 0, n_diag,
+                                    None if offsets is None else offsets.ctypes.data,
+                                    None if h0 is None else h0.ctypes.data,
+                                    None if hk is None else hk.ctypes.data, None, None, None)
+
+    assert create(0, offs, H0d) == -1                                   # n_diag < 1
+    assert create(2 * d, offs, H0d) == -1                               # n_diag > 2 d - 1
+    assert create(3, None, H0d) == -1                                   # offsets NULL
+    assert create(3, offs, None) == -1                                  # H0_diags NULL
+    assert create(3, np.array([0, 1, 1], np.int32), H0d) == -1          # repeated offset
+    assert b"repeated" in lib.og_last_error()
+    assert create(3, np.array([0, 1, -d], np.int32), H0d) == -1         # offset outside (-d, d)
+    assert create(3, offs, H0d, K=1) == -1                              # Hk_diags NULL with K = 1
+    # a non-Hermitian H0 given by diagonals is found before any device work
+    bad = H0d.copy()
+    bad[1, 0] = 1.0                                                     # H0[0, 1] = 1 without H0[1, 0]
+    assert create(3, offs, bad) == -3
+
+
 @pytest.mark.gpu
 def test_call_order_workspace_and_stability_errors():
     import torch

@@ -155,3 +155,33 @@ def test_tiny_dimension_d1_and_d2():
                         wl.controls_uniform(50 + d, 17, 1))
         for path in ("banded", "dense"):
             _check(w, w.u, "f64", path, "exact", tag=f"tiny d={d}")
+
+
+def _diagonals(mats, offsets):
+    d = mats.shape[-1]
+    out = np.zeros(mats.shape[:-2] + (len(offsets), d), np.complex128)
+    for t, o in enumerate(offsets):
+        for i in range(max(0, -o), min(d, d - o)):
+            out[..., t, i] = mats[..., i, i + o]
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_create_banded_equals_dense_create(prec):
+    """og_create_banded with the diagonals of the C3-shaped operators gives
+    bitwise the results of og_create with the dense matrices."""
+    from paper_1609_03170_amd import Problem
+
+    w = wl.config_c3(batch=2, n_t=12)
+    mats = np.concatenate([w.H0[None], w.Hk, w.c_ops])
+    offsets = sorted({int(j - i) for m in mats for i, j in zip(*np.nonzero(m))})
+    say(f"[case] create_banded C3-shape prec={prec} offsets={offsets}")
+    pb = Problem.from_banded(offsets, _diagonals(w.H0, offsets), _diagonals(w.Hk, offsets),
+                             _diagonals(w.c_ops, offsets), w.gammas, prec=prec, gmode="exact")
+    assert pb.path == "banded"
+    a = gpu_eval(w, w.u, prec=prec, gmode="exact", problem=pb)
+    pb.close()
+    b = gpu_eval(w, w.u, prec=prec, path="auto", gmode="exact")
+    b[3].close()
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
