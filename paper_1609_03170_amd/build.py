@@ -1,7 +1,10 @@
 """Compile the HIP sources of the library into paper_1609_03170_amd/libopengrape.so.
 
 gfx950 only.  Every HIP translation unit is built with packed-FP32
-instruction selection disabled (-packed-fp32-ops off)."""
+instruction selection disabled (-packed-fp32-ops off) and without automatic
+floating-point contraction (-ffp-contract=off): the device code writes its
+fused multiply-adds explicitly, so an operation rounds the same way in every
+kernel that performs it."""
 from __future__ import annotations
 
 import os
@@ -22,6 +25,7 @@ FLAGS = [
     "-fPIC",
     "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"),
 ]
 

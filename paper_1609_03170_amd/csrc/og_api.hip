@@ -493,17 +493,22 @@ struct Engine : EngineBase {
   // resonator) or by the library maxima.  Exact-count instantiations were
   // measured slower: they hoist every tap load of the four rows of a thread
   // and fall to two waves per SIMD.
-  template <int MODE, int NA, int ND, bool EXACT>
+  template <int MODE, int NA, int ND>
   void launch_band_v(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
-    og::band_stage_kernel<T, MODE, NA, ND, EXACT><<<stage_grid(), 256, 0, st>>>(ops, io, tiles, ntile, d, coef);
+    og::band_stage_kernel<T, MODE, NA, ND><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(ops, io, tiles, ntile,
+                                                                                          d, coef);
   }
+  // compiled tap counts (NA, ND) that hold the operator: the smallest for
+  // padded taps (every one is loaded), (8, 4) or more otherwise
   template <int MODE>
   void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
     const int na = ops.nA, nd = ops.nD;
-    if (na <= 8 && nd <= 4)
-      launch_band_v<MODE, 8, 4, false>(ops, io, coef);
+    if (og::StageCfg<T>::PAD && na <= 5 && nd <= 3)
+      launch_band_v<MODE, 5, 3>(ops, io, coef);
+    else if (na <= 8 && nd <= 4)
+      launch_band_v<MODE, 8, 4>(ops, io, coef);
     else
-      launch_band_v<MODE, og::MAXA, og::MAXD, false>(ops, io, coef);
+      launch_band_v<MODE, og::MAXA, og::MAXD>(ops, io, coef);
   }
 
   // One Runge-Kutta stage for the whole batch: out = f(L_dir(in)).
@@ -953,14 +958,16 @@ struct Engine : EngineBase {
 
   template <int MODE, int NA, int ND>
   void launch_slots_v(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
-    og::band_stage_slots_kernel<T, MODE, NA, ND><<<dim3((unsigned)(n * ntile)), 256, 0, st>>>(
+    og::band_stage_slots_kernel<T, MODE, NA, ND><<<dim3((unsigned)(n * ntile)), og::stage_threads<T>(), 0, st>>>(
         dir[dr].band, tab, in_role, out_role, coef, ctx->status_dev, tiles, ntile, d);
   }
   template <int MODE>
   og_status launch_slots(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
     const og::BandOps<T>& ops = dir[dr].band;
     const long pidx = ctx->prof_begin(st);
-    if (ops.nA <= 8 && ops.nD <= 4)
+    if (og::StageCfg<T>::PAD && ops.nA <= 5 && ops.nD <= 3)
+      launch_slots_v<MODE, 5, 3>(dr, tab, n, in_role, out_role, coef);
+    else if (ops.nA <= 8 && ops.nD <= 4)
       launch_slots_v<MODE, 8, 4>(dr, tab, n, in_role, out_role, coef);
     else
       launch_slots_v<MODE, og::MAXA, og::MAXD>(dr, tab, n, in_role, out_role, coef);

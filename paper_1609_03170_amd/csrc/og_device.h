@@ -41,21 +41,27 @@ template <typename T>
 __device__ __forceinline__ cpx<T> cscale(T s, cpx<T> a) { return mkc<T>(s * a.re, s * a.im); }
 template <typename T>
 __device__ __forceinline__ cpx<T> conjg(cpx<T> a) { return mkc<T>(a.re, -a.im); }
+// Fused multiply-add with one rounding.  The library is compiled without
+// automatic contraction, so every product and sum rounds exactly as
+// written here and an operation gives the same bits in every kernel.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 // acc += a * b
 template <typename T>
 __device__ __forceinline__ void cfma(cpx<T>& acc, cpx<T> a, cpx<T> b) {
-  acc.re += a.re * b.re - a.im * b.im;
-  acc.im += a.re * b.im + a.im * b.re;
+  acc.re = fmad(a.re, b.re, fmad(-a.im, b.im, acc.re));
+  acc.im = fmad(a.re, b.im, fmad(a.im, b.re, acc.im));
 }
 // acc += a * conj(b)
 template <typename T>
 __device__ __forceinline__ void cfmac(cpx<T>& acc, cpx<T> a, cpx<T> b) {
-  acc.re += a.re * b.re + a.im * b.im;
-  acc.im += a.im * b.re - a.re * b.im;
+  acc.re = fmad(a.re, b.re, fmad(a.im, b.im, acc.re));
+  acc.im = fmad(a.im, b.re, fmad(-a.re, b.im, acc.im));
 }
+// a * conj(b)
 template <typename T>
 __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
-  return mkc<T>(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
+  return mkc<T>(fmad(a.re, b.re, a.im * b.im), fmad(a.im, b.re, -(a.re * b.im)));
 }
 
 // Map the hardware block id to a logical one so that consecutive logical
@@ -125,24 +131,25 @@ __device__ __forceinline__ void two_sum_update(T& hi, T& lo, T delta) {
   hi = h2;
 }
 
-// Write the 32 x 32 tile held in v[4] (rows ty + 8q, column tx) to out at
+// Write the 32 x 32 tile held in v[NQ] (rows ty + (32/NQ) q, column tx) to out at
 // (I0, J0) and, with MIRROR, its conjugate transpose at (J0, I0); on a
 // diagonal tile the lower triangle is taken from the conjugated upper one.
 // Without MIRROR only the upper-triangular tiles are written: used for the
 // compensation term of the state, which is read at those tiles only (the
 // readers of whole matrices take a lower tile from its mirror).
-template <typename T, bool MIRROR = true>
+template <typename T, bool MIRROR = true, int NQ = 4>
 __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d, int I0, int J0,
-                                                const cpx<T> (&v)[4], cpx<T> (*tile)[TS + 1], int tx,
+                                                const cpx<T> (&v)[NQ], cpx<T> (*tile)[TS + 1], int tx,
                                                 int ty) {
+  constexpr int RS = TS / NQ;
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) tile[ty + 8 * q][tx] = v[q];
+  for (int q = 0; q < NQ; ++q) tile[ty + RS * q][tx] = v[q];
   __syncthreads();
   const bool diag = (I0 == J0);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = ty + 8 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int r = ty + RS * q;
     const int i = I0 + r, j = J0 + tx;
     if (i < d && j < d) {
       cpx<T> z = (!diag || r <= tx) ? tile[r][tx] : conjg(tile[tx][r]);
@@ -151,8 +158,8 @@ __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d,
   }
   if (MIRROR && !diag) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = ty + 8 * q;
+    for (int q = 0; q < NQ; ++q) {
+      const int r = ty + RS * q;
       const int i = J0 + r, j = I0 + tx;
       if (i < d && j < d) out[(long)i * d + j] = conjg(tile[tx][r]);
     }
@@ -190,15 +197,32 @@ __device__ __forceinline__ ProbPtr<T> resolve_strided(const StageIO<T>& io, int 
   return P;
 }
 
-template <typename T, int MODE>
+// The state elements that the epilogue adds to (rows ty + (32/NQ) q,
+// column tx of the tile), loaded by the caller together with its own loads
+// so that their latency overlaps with the right-hand side.
+template <typename T, int MODE, int NQ = 4>
+__device__ __forceinline__ void load_own(const ProbPtr<T>& P, int d, int I0, int J0, int tx, int ty,
+                                         cpx<T> (&sh)[NQ], cpx<T> (&sl)[NQ]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = min(I0 + ty + (TS / NQ) * q, d - 1), j = min(J0 + tx, d - 1);
+    const long e = (long)i * d + j;
+    sh[q] = mkc<T>(0, 0);
+    sl[q] = mkc<T>(0, 0);
+    if (MODE != SM_SCALE) sh[q] = P.shi[e];
+    if (MODE == SM_FINAL && P.slo) sl[q] = P.slo[e];
+  }
+}
+
+template <typename T, int MODE, int NQ = 4>
 __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int nex, int* status, int d, int I0,
-                                               int J0, const cpx<T> (&val)[4], cpx<T> (*tile)[TS + 1], int tx,
-                                               int ty) {
-  cpx<T> oh[4], ol[4];
+                                               int J0, const cpx<T> (&val)[NQ], const cpx<T> (&sh)[NQ],
+                                               const cpx<T> (&sl)[NQ], cpx<T> (*tile)[TS + 1], int tx, int ty) {
+  cpx<T> oh[NQ], ol[NQ];
   bool bad = false;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = I0 + ty + 8 * q, j = J0 + tx;
+  for (int q = 0; q < NQ; ++q) {
+    const int i = I0 + ty + (TS / NQ) * q, j = J0 + tx;
     oh[q] = mkc<T>(0, 0);
     ol[q] = mkc<T>(0, 0);
     if (i < d && j < d) {
@@ -208,14 +232,14 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
       } else if (MODE == SM_STAGE) {
         // the stage input is rounded to T anyway: the compensation term of
         // the state changes it by at most one ulp and is not read here
-        const cpx<T> h = P.shi[e];
-        oh[q] = mkc<T>(h.re + coef * val[q].re, h.im + coef * val[q].im);
+        const cpx<T> h = sh[q];
+        oh[q] = mkc<T>(fmad(coef, val[q].re, h.re), fmad(coef, val[q].im, h.im));
       } else {  // SM_FINAL
         cpx<T> dl = cscale(coef, val[q]);
         for (int x = 0; x < nex; ++x) dl = cadd(dl, P.ex[x][e]);
-        cpx<T> h = P.shi[e];
+        cpx<T> h = sh[q];
         if (P.slo) {
-          cpx<T> l = P.slo[e];
+          cpx<T> l = sl[q];
           two_sum_update(h.re, l.re, dl.re);
           two_sum_update(h.im, l.im, dl.im);
           ol[q] = l;
@@ -232,8 +256,8 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
     }
   }
   if (MODE == SM_FINAL && bad) *status = 1;
-  write_herm_tile<T>(P.ohi, d, I0, J0, oh, tile, tx, ty);
-  if (MODE == SM_FINAL && P.olo) write_herm_tile<T, false>(P.olo, d, I0, J0, ol, tile, tx, ty);
+  write_herm_tile<T, true, NQ>(P.ohi, d, I0, J0, oh, tile, tx, ty);
+  if (MODE == SM_FINAL && P.olo) write_herm_tile<T, false, NQ>(P.olo, d, I0, J0, ol, tile, tx, ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -242,11 +266,10 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
 //           + sum_t Dl_t(i) conj(Dr_t(j)) Y[i + dp_t, j + dq_t]
 // i.e. A Y + Y A^dag + sum_m gamma_m C_m Y C_m^dag in diagonal storage.
 // One block computes one upper-triangular 32 x 32 tile of one problem with
-// 256 threads; each thread owns rows ty, ty+8, ty+16, ty+24 and column tx.
-// NA / ND bound the number of diagonals / dissipator taps at compile time so
-// that every tap load of an element is issued before the arithmetic; rows
-// and columns outside the matrix are clamped, which is exact because the
-// diagonal-storage coefficient of such a tap is zero.
+// 32 * 32 / NQ threads; each thread owns NQ rows ty + (32 / NQ) q and column
+// tx.  NA / ND bound the number of diagonals / dissipator taps at compile
+// time; rows and columns outside the matrix are clamped, which is exact
+// because the diagonal-storage coefficient of such a tap is zero.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int clampi(int x, int hi) { return x < 0 ? 0 : (x > hi ? hi : x); }
 
@@ -284,7 +307,7 @@ __global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, i
   coef_body(ops, d, K, u + (long)b * u_bs + (long)jslice * K, coef + (long)b * ops.nA * d);
 }
 
-template <typename T, int MODE, int NA, int ND, bool EXACT>
+template <typename T, int MODE, int NA, int ND, int NQ, bool PAD>
 __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const ProbPtr<T>& P,
                                                 const cpx<T>* __restrict__ cb, T coef, int nex, int* status,
                                                 int I0, int J0, int d) {
@@ -294,29 +317,35 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   __shared__ cpx<T> dC[ND][TS];
   __shared__ cpx<T> tile[TS][TS + 1];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  const int nA = EXACT ? NA : ops.nA, nD = EXACT ? ND : ops.nD;
-  for (int e = tid; e < 2 * (nA + nD) * TS; e += 256) {
-    const int side = e / ((nA + nD) * TS);
-    const int rem = e - side * (nA + nD) * TS;
+  const int nA = ops.nA, nD = ops.nD;
+  // Coefficients of the NA / ND taps; taps beyond the operator's own count
+  // get a zero coefficient (their offset is 0).  With PAD the tap loops run
+  // over all NA / ND taps without branches, so that every load of an element
+  // is issued before the arithmetic (fewer waves, more loads in flight);
+  // without PAD they stop at the operator's own counts.
+  for (int e = tid; e < 2 * (NA + ND) * TS; e += TS * TS / NQ) {
+    const int side = e / ((NA + ND) * TS);
+    const int rem = e - side * (NA + ND) * TS;
     const int s = rem / TS, r = rem - s * TS;
     const int idx = (side ? J0 : I0) + r;
     cpx<T> v = mkc<T>(0, 0);
     if (idx < d) {
-      if (s < nA)
-        v = cb[s * d + idx];
-      else
-        v = side ? ops.Dr[(s - nA) * d + idx] : ops.Dl[(s - nA) * d + idx];
+      if (s < NA) {
+        if (s < nA) v = cb[s * d + idx];
+      } else if (s - NA < nD) {
+        v = side ? ops.Dr[(s - NA) * d + idx] : ops.Dl[(s - NA) * d + idx];
+      }
     }
-    if (s < nA) {
+    if (s < NA) {
       if (side)
         cC[s][r] = v;
       else
         cR[s][r] = v;
     } else {
       if (side)
-        dC[s - nA][r] = v;
+        dC[s - NA][r] = v;
       else
-        dR[s - nA][r] = v;
+        dR[s - NA][r] = v;
     }
   }
   __syncthreads();
@@ -328,48 +357,69 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   for (int a = 0; a < NA; ++a) colA[a] = clampi(jc + ops.offA[a], dm);
 #pragma unroll
   for (int s = 0; s < ND; ++s) colD[s] = clampi(jc + ops.dq[s], dm);
-  cpx<T> val[4];
+  cpx<T> val[NQ], sh[NQ], sl[NQ];
+  if (PAD) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int r = ty + 8 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int r = ty + (TS / NQ) * q;
     const int ic = min(I0 + r, dm);
     const unsigned rowi = __umul24(ic, d);
     cpx<T> yr[NA], yc[NA], yd[ND];
 #pragma unroll
     for (int a = 0; a < NA; ++a)
-      if (EXACT || a < nA) {
+      if (PAD || a < nA) {
         yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
         yc[a] = ldm(Y, rowi + colA[a]);
       }
 #pragma unroll
     for (int s = 0; s < ND; ++s)
-      if (EXACT || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+      if (PAD || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
     cpx<T> acc = mkc<T>(0, 0);
 #pragma unroll
     for (int a = 0; a < NA; ++a)
-      if (EXACT || a < nA) {
+      if (PAD || a < nA) {
         cfma(acc, cR[a][r], yr[a]);
         cfmac(acc, yc[a], cC[a][tx]);
       }
 #pragma unroll
     for (int s = 0; s < ND; ++s)
-      if (EXACT || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[s]);
+      if (PAD || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[s]);
     val[q] = acc;
   }
-  stage_epilogue<T, MODE>(P, coef, nex, status, d, I0, J0, val, tile, tx, ty);
+  if (!PAD) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
+  stage_epilogue<T, MODE, NQ>(P, coef, nex, status, d, I0, J0, val, sh, sl, tile, tx, ty);
+}
+
+// Launch shape of the banded stage per working precision: rows of the
+// tile per thread (NQ; the block has 32 * 32 / NQ threads) and padded taps.
+// float32 runs 512-thread blocks with every tap load in flight; float64
+// keeps 256-thread blocks whose loads stop at the operator's own taps
+// (measured faster for its twice larger registers).
+template <typename T>
+struct StageCfg {
+  static constexpr int NQ = 4;
+  static constexpr bool PAD = false;
+};
+template <>
+struct StageCfg<float> {
+  static constexpr int NQ = 2;
+  static constexpr bool PAD = true;
+};
+template <typename T>
+constexpr int stage_threads() {
+  return TS * TS / StageCfg<T>::NQ;
 }
 
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
-template <typename T, int MODE, int NA, int ND, bool EXACT>
-__global__ __launch_bounds__(256) void band_stage_kernel(BandOps<T> ops, StageIO<T> io,
-                                                         const int2* __restrict__ tiles, int ntile, int d,
-                                                         const cpx<T>* __restrict__ coef) {
+template <typename T, int MODE, int NA, int ND>
+__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
+    BandOps<T> ops, StageIO<T> io, const int2* __restrict__ tiles, int ntile, int d,
+    const cpx<T>* __restrict__ coef) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   const int2 tt = tiles[t];
-  const int nA = EXACT ? NA : ops.nA;
-  band_stage_body<T, MODE, NA, ND, EXACT>(ops, resolve_strided(io, b), coef + (long)b * nA * d, io.coef, io.nex,
-                                         io.status, tt.x * TS, tt.y * TS, d);
+  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD>(
+      ops, resolve_strided(io, b), coef + (long)b * ops.nA * d, io.coef, io.nex, io.status, tt.x * TS, tt.y * TS, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,7 +459,7 @@ __global__ __launch_bounds__(256) void band_coef_slots_kernel(BandOps<T> ops, Sl
 }
 
 template <typename T, int MODE, int NA, int ND>
-__global__ __launch_bounds__(256) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
+__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
                                                                int out_role, T coef, int* status,
                                                                const int2* __restrict__ tiles, int ntile,
                                                                int d) {
@@ -424,7 +474,8 @@ __global__ __launch_bounds__(256) void band_stage_slots_kernel(BandOps<T> ops, S
   P.ohi = const_cast<cpx<T>*>(role_ptr(s, out_role));
   P.olo = out_role == R_OUT ? s.o_lo : nullptr;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  band_stage_body<T, MODE, NA, ND, false>(ops, P, s.coef, coef, 0, status, tt.x * TS, tt.y * TS, d);
+  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD>(ops, P, s.coef, coef, 0, status, tt.x * TS,
+                                                                     tt.y * TS, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,6 +494,9 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
   const int2 tt = tiles[t];
   const int I0 = tt.x * TS, J0 = tt.y * TS;
   const cpx<T>* __restrict__ Xb = X + (long)b * x_s;
+  const ProbPtr<T> P = resolve_strided(io, b);
+  cpx<T> sh[4], sl[4];
+  load_own<T, MODE>(P, d, I0, J0, tx, ty, sh, sl);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = ty + 8 * q;
@@ -457,7 +511,7 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
     const int i = I0 + r, j = J0 + tx;
     val[q] = (i < d && j < d) ? cadd(Xb[(long)i * d + j], conjg(tT[tx][r])) : mkc<T>(0, 0);
   }
-  stage_epilogue<T, MODE>(resolve_strided(io, b), io.coef, io.nex, io.status, d, I0, J0, val, tile, tx, ty);
+  stage_epilogue<T, MODE>(P, io.coef, io.nex, io.status, d, I0, J0, val, sh, sl, tile, tx, ty);
 }
 
 // ---------------------------------------------------------------------------
