@@ -145,6 +145,36 @@ og_status og_create_banded(og_ctx **out, int d, int K, int J, int n_diag, const 
                            const void *H0_diags, const void *Hk_diags, const void *c_diags,
                            const double *gamma, const og_options *opt);
 
+/*
+ * Adaptive steps (the adaptive Runge-Kutta integration of every slice,
+ * Sec. III.A): with rtol > 0 every slice of the forward sweep, of its
+ * checkpoint recompute and of the adjoint sweep is integrated by the
+ * embedded Dormand-Prince 5(4) pair with step-size control per problem:
+ * an attempt of size h' = min(h, time left in the slice) is accepted when
+ * sqrt(mean_c (e_c / (atol + rtol max(|y_c|, |y5_c|)))^2) <= 1 over the real
+ * and imaginary parts c of all matrix elements (e: difference of the order-5
+ * and order-4 solutions, y5: the order-5 solution), and the next proposal is
+ * h' min(fmax, max(0.2, 0.9 err^(-1/5))) with fmax = 1 after a rejection, 5
+ * otherwise (h' max(0.2, 0.9 err^(-1/5)) after a rejection).  The first
+ * slice of a sweep starts with h = dt; the proposal carries over between
+ * slices.  n_sub and the fixed-step stability check are then not used.
+ * rtol = 0 returns to fixed RK4 steps.  Only OG_GRAD_GRAPE1 contexts
+ * (OG_ERR_ARG otherwise); servers refuse requests while it is on.
+ * og_workspace_bytes grows by 9 state matrices per problem; query it after
+ * this call.  Each attempt ends with one stream synchronization (the host
+ * learns whether any problem is still inside the slice).
+ */
+og_status og_set_adaptive(og_ctx *ctx, double rtol, double atol);
+
+/*
+ * Step counts of the last evaluation, per problem: counts (host, long
+ * B x 4) = [accepted forward, rejected forward, accepted adjoint, rejected
+ * adjoint] (the checkpoint recompute repeats the forward steps and is not
+ * counted).  Synchronous.  OG_ERR_ORDER before og_adjoint or without
+ * adaptive steps.
+ */
+og_status og_adaptive_stats(og_ctx *ctx, long *counts);
+
 /* Free the context and its device memory (synchronizes the device). */
 og_status og_destroy(og_ctx *ctx);
 

@@ -39,7 +39,7 @@ EXPORTS = (
     "og_forward", "og_cost", "og_adjoint", "og_gradient", "og_profile", "og_profile_read",
     "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
     "og_server_destroy", "og_status_string", "og_last_error", "og_gradient_sum", "og_set_penalty",
-    "og_filter_apply", "og_filter_grad", "og_create_banded",
+    "og_filter_apply", "og_filter_grad", "og_create_banded", "og_set_adaptive", "og_adaptive_stats",
 )
 
 
@@ -101,6 +101,10 @@ def load_library(path: str = LIB_PATH):
     lib.og_gradient_sum.restype = i
     lib.og_set_penalty.argtypes = [vp, vp, d]
     lib.og_set_penalty.restype = i
+    lib.og_set_adaptive.argtypes = [vp, d, d]
+    lib.og_set_adaptive.restype = i
+    lib.og_adaptive_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_long)]
+    lib.og_adaptive_stats.restype = i
     lib.og_filter_apply.argtypes = [i, i, i, i, d, d, d, vp, vp, vp]
     lib.og_filter_apply.restype = i
     lib.og_filter_grad.argtypes = [i, i, i, i, d, d, d, i, vp, vp, vp]
@@ -328,6 +332,20 @@ class Problem:
             out = torch.empty((n_t, self.K), dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
             _check(self._lib.og_gradient_sum(self._ctx, out.data_ptr(), int(acc), _stream_ptr(self.device)))
+        return out
+
+    def set_adaptive(self, rtol, atol=0.0):
+        """Adaptive Dormand-Prince 5(4) steps with the given tolerances
+        (rtol = 0: fixed RK4 steps again).  Query workspace_bytes afterwards."""
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_set_adaptive(self._ctx, float(rtol), float(atol)))
+
+    def adaptive_stats(self, B):
+        """[B, 4] numpy int64: accepted / rejected steps of the forward and
+        adjoint sweeps of the last evaluation."""
+        out = np.zeros((int(B), 4), dtype=np.int64)
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_adaptive_stats(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_long))))
         return out
 
     def set_penalty(self, A, beta):

@@ -201,6 +201,7 @@ struct EngineBase {
   virtual og_status adjoint(const void* sigma, hipStream_t st) = 0;
   virtual og_status gradient(double* grad, hipStream_t st) = 0;
   virtual og_status gradient_sum(double* grad, int accumulate, hipStream_t st) = 0;
+  virtual og_status adaptive_stats(long* counts) = 0;
   // continuous batching (og_server_*)
   virtual og_status serve_submit(const og_request& r, hipStream_t st) = 0;
   virtual og_status serve_step(int max_slices, hipStream_t st, std::vector<long>& done) = 0;
@@ -229,6 +230,9 @@ struct og_ctx {
   double pen_beta = 0.0;
   og::CooEntry* pen_coo = nullptr;
   int pen_nnz = 0;
+  // adaptive steps (og_set_adaptive): relative / absolute tolerances, 0 = fixed steps
+  double ad_rtol = 0.0, ad_atol = 0.0;
+  int* host_flag = nullptr;  // pinned: problems still active after an attempt
   // kernel timing samples (og_profile)
   int prof_every = 0;
   long prof_counter = 0;
@@ -416,7 +420,8 @@ struct Engine : EngineBase {
   };
   enum {
     L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
-    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_COEF, L_GRAD, L_PEN, L_N
+    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_COEF, L_GRAD, L_PEN,
+    L_DPK, L_DPY, L_DPD, L_DPP, L_DPC, L_DPCK, L_N
   };
 
   int stride_for(int nt) const {
@@ -461,6 +466,14 @@ struct Engine : EngineBase {
     // per-slice gradient partial sums, one per row chunk of the contraction
     sz[L_GRAD] = (size_t)b * nt * og::NCH * std::max(K, 1) * sizeof(double);
     sz[L_PEN] = (size_t)b * (nt + 1) * sizeof(double);
+    if (ctx->ad_rtol > 0.0) {
+      sz[L_DPK] = 7 * m;
+      sz[L_DPY] = m;
+      sz[L_DPD] = m;
+      sz[L_DPP] = (size_t)b * og::NCH * sizeof(double);
+      sz[L_DPC] = kDpCtl * dpctl_bytes(b);
+      sz[L_DPCK] = (size_t)nseg * b * 2 * sizeof(double);
+    }
     size_t pos = 0;
     for (int i = 0; i < L_N; ++i) {
       L.off[i] = pos;
@@ -484,6 +497,7 @@ struct Engine : EngineBase {
     io.o_s = E;
     io.ex_s = E;
     io.status = ctx->status_dev;
+    io.active = stage_active;
     return io;
   }
 
@@ -691,6 +705,111 @@ struct Engine : EngineBase {
 
   og::cpx<T>* slot(og::cpx<T>* base, int idx) const { return base ? base + (long)idx * B * E : nullptr; }
 
+  // ----- adaptive steps (og_set_adaptive) -----
+  // Controllers: the forward sweep, its checkpoint recompute (restarted from
+  // the controller state stored with every checkpoint) and the adjoint.
+  enum { DP_FWD = 0, DP_REC = 1, DP_ADJ = 2, kDpCtl = 3 };
+  static constexpr int kMaxAttempts = 100000;  // per slice
+  og::cpx<T>* dpk = nullptr;  // k_1..k_7, B matrices each
+  og::cpx<T>* dpy = nullptr;  // stage input Y_i
+  og::cpx<T>* dpd = nullptr;  // increment of the attempt
+  double* dpp = nullptr;      // error partial sums, B x NCH
+  og::DpCtl dpc[kDpCtl]{};
+  double* dpck = nullptr;     // (h, rejected) per checkpoint and problem
+  const int* stage_active = nullptr;  // gate of the banded stage launches
+
+  static size_t dpctl_bytes(int b) {
+    return align256((size_t)b * (5 * sizeof(double) + 3 * sizeof(int)) + sizeof(int));
+  }
+  static og::DpCtl carve_ctl(char* p, int b) {
+    og::DpCtl c{};
+    c.h = reinterpret_cast<double*>(p);
+    c.t_rem = c.h + b;
+    c.hu = c.t_rem + b;
+    c.n_acc = reinterpret_cast<long long*>(c.hu + b);
+    c.n_rej = c.n_acc + b;
+    c.act = reinterpret_cast<int*>(c.n_rej + b);
+    c.acc = c.act + b;
+    c.rej = c.acc + b;
+    c.n_active = c.rej + b;
+    return c;
+  }
+
+  // One slice of the adaptive integrator (Dormand-Prince 5(4) with step
+  // control) on the state (hi, lo) in place, for every problem.
+  og_status adaptive_slice(int dr, int jslice, og::cpx<T>* hi, og::cpx<T>* lo, const og::DpCtl& c) {
+    static const double A[7][6] = {
+        {0, 0, 0, 0, 0, 0},
+        {1.0 / 5, 0, 0, 0, 0, 0},
+        {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+        {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+        {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+        {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+        {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+    static const double Bw[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+    static const double Bh[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100,
+                                 1.0 / 40};
+    og::DpRow bw{}, ew{};
+    for (int i = 0; i < 7; ++i) {
+      bw.c[i] = Bw[i];
+      ew.c[i] = Bw[i] - Bh[i];
+    }
+    const long mst = (long)B * E;
+    const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
+    OG_TRY(assemble(dr, jslice));
+    og::dp_begin_kernel<<<1, 256, 0, st>>>(c, B, dt);
+    OG_CHECK_LAUNCH();
+    stage_active = c.act;
+    for (int attempt = 0;; ++attempt) {
+      if (attempt >= kMaxAttempts) {
+        stage_active = nullptr;
+        return fail(OG_ERR_UNSTABLE_DT, "adaptive step control did not finish slice " + std::to_string(jslice));
+      }
+      og_status s_ = stage(dr, og::SM_SCALE, jslice, hi, nullptr, nullptr, dpk, nullptr, T(1));
+      for (int i = 1; i < 7 && s_ == OG_OK; ++i) {
+        og::DpRow a{};
+        for (int l = 0; l < i; ++l) a.c[l] = A[i][l];
+        og::dp_combine_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(hi, dpk, mst, E, i, a, c.hu, c.act, dpy, E);
+        if (hipGetLastError() != hipSuccess) s_ = fail(OG_ERR_DEVICE, "combine launch failed");
+        if (s_ == OG_OK) s_ = stage(dr, og::SM_SCALE, jslice, dpy, nullptr, nullptr, dpk + i * mst, nullptr, T(1));
+      }
+      if (s_ != OG_OK) {
+        stage_active = nullptr;
+        return s_;
+      }
+      og::dp_error_kernel<T><<<dim3((unsigned)og::NCH, (unsigned)B), 256, 0, st>>>(
+          hi, dpk, mst, E, bw, ew, c.hu, c.act, ctx->ad_rtol, ctx->ad_atol, dpd, dpp, E);
+      OG_CHECK_LAUNCH();
+      og::dp_control_kernel<<<1, 256, 0, st>>>(c, dpp, B, 2.0 * (double)E);
+      OG_CHECK_LAUNCH();
+      og::StageIO<T> io = io_base();
+      io.in = dpd;
+      io.shi = hi;
+      io.slo = lo;
+      io.ohi = hi;
+      io.olo = lo;
+      og::dp_accept_kernel<T><<<stage_grid(), 256, 0, st>>>(io, c.acc, tiles, ntile, d);
+      OG_CHECK_LAUNCH();
+      OG_HIP(hipMemcpyAsync(ctx->host_flag, c.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+      OG_HIP(hipStreamSynchronize(st));
+      if (*ctx->host_flag == 0) break;
+    }
+    stage_active = nullptr;
+    return OG_OK;
+  }
+
+  og_status adaptive_stats(long* counts) override {
+    if (ctx->ad_rtol <= 0.0 || !dpk) return fail(OG_ERR_ORDER, "no adaptive evaluation has run");
+    std::vector<long long> v((size_t)4 * B);
+    OG_HIP(hipMemcpy(v.data(), dpc[DP_FWD].n_acc, B * sizeof(long long), hipMemcpyDeviceToHost));
+    OG_HIP(hipMemcpy(v.data() + B, dpc[DP_FWD].n_rej, B * sizeof(long long), hipMemcpyDeviceToHost));
+    OG_HIP(hipMemcpy(v.data() + 2 * B, dpc[DP_ADJ].n_acc, B * sizeof(long long), hipMemcpyDeviceToHost));
+    OG_HIP(hipMemcpy(v.data() + 3 * B, dpc[DP_ADJ].n_rej, B * sizeof(long long), hipMemcpyDeviceToHost));
+    for (int b = 0; b < B; ++b)
+      for (int q = 0; q < 4; ++q) counts[4 * b + q] = (long)v[(size_t)q * B + b];
+    return OG_OK;
+  }
+
   og_status bind(void* ws, int b, int nt) {
     const Layout L = layout(b, nt);
     char* p = static_cast<char*>(ws);
@@ -724,6 +843,15 @@ struct Engine : EngineBase {
     acoef[0] = opt_at(L_COEF, banded);
     acoef[1] = banded ? acoef[0] + (size_t)b * og::MAXA * d : nullptr;
     grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);
+    if (ctx->ad_rtol > 0.0) {
+      dpk = at(L_DPK);
+      dpy = at(L_DPY);
+      dpd = at(L_DPD);
+      dpp = reinterpret_cast<double*>(p + L.off[L_DPP]);
+      char* c = p + L.off[L_DPC];
+      for (int i = 0; i < kDpCtl; ++i) dpc[i] = carve_ctl(c + (size_t)i * dpctl_bytes(b), b);
+      dpck = reinterpret_cast<double*>(p + L.off[L_DPCK]);
+    }
     pen = reinterpret_cast<double*>(p + L.off[L_PEN]);
     return OG_OK;
   }
@@ -755,9 +883,23 @@ struct Engine : EngineBase {
     OG_TRY(bind(ws, b, nt));
     OG_TRY(load(rho0, E, cur_hi, cur_lo));
     OG_TRY(penalty_trace(0));
+    const bool ad = ctx->ad_rtol > 0.0;
+    if (ad) {
+      og::dp_init_kernel<<<1, 256, 0, st>>>(dpc[DP_FWD], B, dt);
+      OG_CHECK_LAUNCH();
+    }
     for (int j = 0; j < n_t; ++j) {
-      if (j % S == 0) OG_TRY(copy_state(slot(ck_hi, j / S), slot(ck_lo, j / S), cur_hi, cur_lo));
-      OG_TRY(rk_slice(FWD, j, cur_hi, cur_lo, cur_hi, cur_lo));
+      if (j % S == 0) {
+        OG_TRY(copy_state(slot(ck_hi, j / S), slot(ck_lo, j / S), cur_hi, cur_lo));
+        if (ad) {
+          og::dp_save_kernel<<<1, 256, 0, st>>>(dpc[DP_FWD], B, dpck + (size_t)(j / S) * B * 2);
+          OG_CHECK_LAUNCH();
+        }
+      }
+      if (ad)
+        OG_TRY(adaptive_slice(FWD, j, cur_hi, cur_lo, dpc[DP_FWD]));
+      else
+        OG_TRY(rk_slice(FWD, j, cur_hi, cur_lo, cur_hi, cur_lo));
       OG_TRY(penalty_trace(j + 1));
     }
     if (rhoT) {
@@ -804,11 +946,29 @@ struct Engine : EngineBase {
     const T h = (T)(dt / nsub);
     OG_TRY(load(sigma, 0, lam_hi, lam_lo));
     OG_TRY(penalty_inject());
+    const bool ad = ctx->ad_rtol > 0.0;
+    if (ad) {
+      og::dp_init_kernel<<<1, 256, 0, st>>>(dpc[DP_ADJ], B, dt);
+      OG_CHECK_LAUNCH();
+      og::dp_init_kernel<<<1, 256, 0, st>>>(dpc[DP_REC], B, dt);
+      OG_CHECK_LAUNCH();
+    }
     for (int seg = n_seg - 1; seg >= 0; --seg) {
       const int j0 = seg * S, j1 = std::min(n_t, j0 + S), n = j1 - j0;
       OG_TRY(copy_state(slot(sg_hi, 0), slot(sg_lo, 0), slot(ck_hi, seg), slot(ck_lo, seg)));
-      for (int jj = 0; jj < n; ++jj)
-        OG_TRY(rk_slice(FWD, j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1), slot(sg_lo, jj + 1)));
+      if (ad) {
+        // the recompute restarts from the controller state stored with the
+        // checkpoint, so it takes the forward sweep's steps exactly
+        og::dp_load_kernel<<<1, 256, 0, st>>>(dpc[DP_REC], B, dpck + (size_t)seg * B * 2);
+        OG_CHECK_LAUNCH();
+        for (int jj = 0; jj < n; ++jj) {
+          OG_TRY(copy_state(slot(sg_hi, jj + 1), slot(sg_lo, jj + 1), slot(sg_hi, jj), slot(sg_lo, jj)));
+          OG_TRY(adaptive_slice(FWD, j0 + jj, slot(sg_hi, jj + 1), slot(sg_lo, jj + 1), dpc[DP_REC]));
+        }
+      } else {
+        for (int jj = 0; jj < n; ++jj)
+          OG_TRY(rk_slice(FWD, j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1), slot(sg_lo, jj + 1)));
+      }
       for (int jj = n - 1; jj >= 0; --jj) {
         const int j = j0 + jj;
         if (!exact) {
@@ -816,7 +976,10 @@ struct Engine : EngineBase {
           const og::cpx<T>* Ls[1] = {lam_hi};
           const double cf[1] = {dt};
           OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
-          OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
+          if (ad)
+            OG_TRY(adaptive_slice(ADJ, j, lam_hi, lam_lo, dpc[DP_ADJ]));
+          else
+            OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
           OG_TRY(penalty_inject());
           continue;
         }
@@ -899,6 +1062,7 @@ struct Engine : EngineBase {
 
   og_status serve_submit(const og_request& r, hipStream_t s) override {
     if (!banded) return fail(OG_ERR_SHAPE, "serving needs the banded path");
+    if (ctx->ad_rtol > 0.0) return fail(OG_ERR_ARG, "serving runs fixed steps; disable adaptive steps");
     if (r.ws_bytes < ws_bytes(1, r.n_t)) return fail(OG_ERR_WORKSPACE, "request workspace too small");
     Slot sl;
     sl.r = r;
@@ -1365,8 +1529,30 @@ og_status og_destroy(og_ctx* ctx) {
   if (ctx->status_dev) (void)hipFree(ctx->status_dev);
   if (ctx->umax_dev) (void)hipFree(ctx->umax_dev);
   if (ctx->pen_coo) (void)hipFree(ctx->pen_coo);
+  if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
   delete ctx;
   return OG_OK;
+}
+
+og_status og_set_adaptive(og_ctx* ctx, double rtol, double atol) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (!(rtol >= 0.0) || !(atol >= 0.0) || !std::isfinite(rtol) || !std::isfinite(atol))
+    return fail(OG_ERR_ARG, "tolerances must be finite and >= 0");
+  if (rtol > 0.0 && ctx->opt.gmode != OG_GRAD_GRAPE1)
+    return fail(OG_ERR_ARG, "adaptive steps support the first-order gradient (OG_GRAD_GRAPE1) only");
+  if (rtol > 0.0 && !ctx->host_flag) OG_HIP(hipHostMalloc((void**)&ctx->host_flag, sizeof(int)));
+  ctx->ad_rtol = rtol;
+  ctx->ad_atol = rtol > 0.0 ? atol : 0.0;
+  ctx->phase = 0;
+  return OG_OK;
+}
+
+og_status og_adaptive_stats(og_ctx* ctx, long* counts) {
+  g_err.clear();
+  if (!ctx || !ctx->eng || !counts) return fail(OG_ERR_ARG, "ctx or counts is NULL");
+  if (ctx->phase < 2) return fail(OG_ERR_ORDER, "og_adaptive_stats before og_adjoint");
+  return ctx->eng->adaptive_stats(counts);
 }
 
 size_t og_workspace_bytes(const og_ctx* ctx, int B, int n_t) {
@@ -1404,6 +1590,7 @@ static og_status check_stability(og_ctx* ctx, const double* u, long rows, double
     lo = std::min(lo, ctx->h0_diag[i] - r);
   }
   for (int k = 0; k < K; ++k) frob += um[k] * ctx->hk_frob[k];
+  if (ctx->ad_rtol > 0.0) return OG_OK;  // adaptive steps choose their own size
   const double span = std::min(hi - lo, 2.0 * frob);
   const double h = dt / ctx->opt.n_sub;
   if (h * span > 2.83 || h * ctx->diss_bound > 2.78) {

@@ -96,6 +96,7 @@ struct StageIO {
   int nex;
   T coef;
   int* status;        // set to 1 when a non-finite value is produced
+  const int* active;  // banded: problems with active[b] = 0 are skipped (nullptr: none)
 };
 
 // Diagonal storage of the generator pieces for one direction (forward uses
@@ -417,6 +418,7 @@ __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
     const cpx<T>* __restrict__ coef) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
+  if (io.active && !io.active[b]) return;
   const int2 tt = tiles[t];
   band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD>(
       ops, resolve_strided(io, b), coef + (long)b * ops.nA * d, io.coef, io.nex, io.status, tt.x * TS, tt.y * TS, d);
@@ -1211,6 +1213,203 @@ __global__ __launch_bounds__(256) void umax_kernel(const double* __restrict__ u,
     }
     if (threadIdx.x == 0) out[(long)blockIdx.x * K + k] = sh[0];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive steps: the embedded Dormand-Prince 5(4) pair with step-size
+// control, one controller per problem (the adaptive integrator of
+// Sec. III.A).  Per attempt: the seven stage derivatives k_i = L(Y_i) (the
+// stage kernels with coef 1), Y_i = y + hu sum_{l<i} a_il k_l
+// (dp_combine_kernel), the increment and error norm (dp_error_kernel), the
+// controller (dp_control_kernel) and the compensated update of the accepted
+// problems (dp_accept_kernel).  Controller state in device memory:
+// ---------------------------------------------------------------------------
+struct DpCtl {
+  double* h;      // step proposal (carried across slices)
+  double* t_rem;  // time left in the current slice
+  double* hu;     // step of the current attempt, min(h, t_rem)
+  int* act;       // 1 while the slice is unfinished
+  int* acc;       // 1 when the current attempt was accepted
+  int* rej;       // 1 right after a rejected attempt
+  long long* n_acc;
+  long long* n_rej;
+  int* n_active;  // problems still active after the last control step
+};
+
+struct DpRow {
+  double c[7];  // one row of coefficients (a_il, b_i or e_i)
+};
+
+// a sweep starts with the proposal h0, no rejection and zero counters
+__global__ __launch_bounds__(256) void dp_init_kernel(DpCtl c, int B, double h0) {
+  for (int b = threadIdx.x; b < B; b += 256) {
+    c.h[b] = h0;
+    c.rej[b] = 0;
+    c.n_acc[b] = 0;
+    c.n_rej[b] = 0;
+  }
+}
+
+// controller state (h, rejected) kept with a checkpoint, and restored from it
+__global__ __launch_bounds__(256) void dp_save_kernel(DpCtl c, int B, double* __restrict__ dst) {
+  for (int b = threadIdx.x; b < B; b += 256) {
+    dst[2 * b] = c.h[b];
+    dst[2 * b + 1] = (double)c.rej[b];
+  }
+}
+__global__ __launch_bounds__(256) void dp_load_kernel(DpCtl c, int B, const double* __restrict__ src) {
+  for (int b = threadIdx.x; b < B; b += 256) {
+    c.h[b] = src[2 * b];
+    c.rej[b] = src[2 * b + 1] != 0.0 ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void dp_begin_kernel(DpCtl c, int B, double dt) {
+  for (int b = threadIdx.x; b < B; b += 256) {
+    c.t_rem[b] = dt;
+    c.act[b] = 1;
+    c.acc[b] = 0;
+    c.hu[b] = c.h[b] >= dt ? dt : c.h[b];
+  }
+  if (threadIdx.x == 0) *c.n_active = B;
+}
+
+// Y = y + sum_{l < n} (hu a_l) k_l, elementwise, for the active problems.
+// k_l of problem b at kb + l * k_st + b * s_s.  grid = (blocks, B).
+template <typename T>
+__global__ __launch_bounds__(256) void dp_combine_kernel(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ kb,
+                                                         long k_st, long s_s, int n, DpRow a,
+                                                         const double* __restrict__ hu, const int* __restrict__ act,
+                                                         cpx<T>* __restrict__ Y, long E) {
+  const int b = blockIdx.y;
+  if (!act[b]) return;
+  T cf[7];
+#pragma unroll
+  for (int l = 0; l < 7; ++l) cf[l] = (T)(hu[b] * a.c[l]);
+  const long o = (long)b * s_s;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < E; e += (long)gridDim.x * 256) {
+    cpx<T> v = y[o + e];
+    for (int l = 0; l < n; ++l) {
+      const cpx<T> k = kb[l * k_st + o + e];
+      v.re = fmad(cf[l], k.re, v.re);
+      v.im = fmad(cf[l], k.im, v.im);
+    }
+    Y[o + e] = v;
+  }
+}
+
+// Increment delta = sum_i (hu b_i) k_i (working precision) and the error
+// e = hu sum_i e_i k_i (float64); partial sums over the chunk of
+// (e_c / (atol + rtol max(|y_c|, |y_c + delta_c|)))^2 over the real and
+// imaginary components c.  grid = (NCH, B).
+template <typename T>
+__global__ __launch_bounds__(256) void dp_error_kernel(const cpx<T>* __restrict__ y, const cpx<T>* __restrict__ kb,
+                                                       long k_st, long s_s, DpRow bw, DpRow ew,
+                                                       const double* __restrict__ hu, const int* __restrict__ act,
+                                                       double rtol, double atol, cpx<T>* __restrict__ delta,
+                                                       double* __restrict__ part, long E) {
+  __shared__ double sh[256];
+  const int ch = blockIdx.x, b = blockIdx.y;
+  if (!act[b]) return;
+  T cb[7];
+  double ce[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    cb[i] = (T)(hu[b] * bw.c[i]);
+    ce[i] = hu[b] * ew.c[i];
+  }
+  const long o = (long)b * s_s;
+  const long e0 = E * ch / NCH, e1 = E * (ch + 1) / NCH;
+  double acc = 0.0;
+  for (long e = e0 + threadIdx.x; e < e1; e += 256) {
+    cpx<T> dl = mkc<T>(0, 0);
+    double er = 0.0, ei = 0.0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const cpx<T> k = kb[i * k_st + o + e];
+      dl.re = fmad(cb[i], k.re, dl.re);
+      dl.im = fmad(cb[i], k.im, dl.im);
+      er = fmad(ce[i], (double)k.re, er);
+      ei = fmad(ce[i], (double)k.im, ei);
+    }
+    delta[o + e] = dl;
+    const cpx<T> yv = y[o + e];
+    const double yr = (double)yv.re, yi = (double)yv.im;
+    const double sr = atol + rtol * fmax(fabs(yr), fabs(yr + (double)dl.re));
+    const double si = atol + rtol * fmax(fabs(yi), fabs(yi + (double)dl.im));
+    const double qr = er / sr, qi = ei / si;
+    acc += qr * qr + qi * qi;
+  }
+  const double v = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part[(long)b * NCH + ch] = v;
+}
+
+// The controller of every active problem: err = sqrt(mean of the squared
+// scaled errors over the n_comp = 2 d^2 components), accept when err <= 1,
+// new proposal h = hu min(fmax, max(0.2, 0.9 err^(-1/5))) (fmax = 1 after a
+// rejection, else 5) or, on rejection, hu max(0.2, 0.9 err^(-1/5)).
+__global__ __launch_bounds__(256) void dp_control_kernel(DpCtl c, const double* __restrict__ part, int B,
+                                                         double n_comp) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < B; b += 256) {
+    if (!c.act[b]) {
+      c.acc[b] = 0;
+      continue;
+    }
+    double s = 0.0;
+    for (int ch = 0; ch < NCH; ++ch) s += part[(long)b * NCH + ch];
+    const double err = sqrt(s / n_comp);
+    const double hu = c.hu[b];
+    const bool clipped = hu == c.t_rem[b];
+    if (err <= 1.0) {
+      const double fmx = c.rej[b] ? 1.0 : 5.0;
+      const double fac = err == 0.0 ? fmx : fmin(fmx, fmax(0.2, 0.9 * pow(err, -0.2)));
+      c.acc[b] = 1;
+      c.t_rem[b] = clipped ? 0.0 : c.t_rem[b] - hu;
+      c.h[b] = hu * fac;
+      c.rej[b] = 0;
+      c.n_acc[b] += 1;
+    } else {
+      c.acc[b] = 0;
+      c.h[b] = hu * fmax(0.2, 0.9 * pow(err, -0.2));
+      c.rej[b] = 1;
+      c.n_rej[b] += 1;
+    }
+    const bool more = c.t_rem[b] > 0.0;
+    c.act[b] = more ? 1 : 0;
+    if (more) {
+      c.hu[b] = c.h[b] >= c.t_rem[b] ? c.t_rem[b] : c.h[b];
+      atomicAdd(&cnt, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *c.n_active = cnt;
+}
+
+// (hi, lo) += delta for the problems whose attempt was accepted: the
+// compensated final-stage epilogue with coefficient 1 on the upper tiles
+// (hi mirrored, lo on the upper tiles).  grid = B * ntile.
+template <typename T>
+__global__ __launch_bounds__(256) void dp_accept_kernel(StageIO<T> io, const int* __restrict__ acc,
+                                                        const int2* __restrict__ tiles, int ntile, int d) {
+  __shared__ cpx<T> tile[TS][TS + 1];
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / ntile, t = L - b * ntile;
+  if (!acc[b]) return;
+  const int2 tt = tiles[t];
+  const int I0 = tt.x * TS, J0 = tt.y * TS;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const ProbPtr<T> P = resolve_strided(io, b);
+  cpx<T> val[4], sh[4], sl[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = I0 + ty + 8 * q, j = J0 + tx;
+    val[q] = (i < d && j < d) ? P.in[(long)i * d + j] : mkc<T>(0, 0);
+  }
+  load_own<T, SM_FINAL>(P, d, I0, J0, tx, ty, sh, sl);
+  stage_epilogue<T, SM_FINAL>(P, T(1), 0, io.status, d, I0, J0, val, sh, sl, tile, tx, ty);
 }
 
 }  // namespace og
