@@ -145,7 +145,8 @@ def extras_leg(args, w, golden):
     """Secondary lines on the same workload, one timed evaluation each: the
     exact (reverse-mode RK4) gradient at the headline batch; single-problem
     latency (B = 1) in both precisions and the batch sweep B = 4, 16, 64, 256;
-    the dense matrix-core path
+    adaptive Dormand-Prince 5(4) steps (B = 32, rtol 1e-5, atol 1e-8) with
+    the mean accepted / rejected steps per slice; the dense matrix-core path
     (complex GEMMs, B = 4) in both precisions, with the MFMA roofline of its
     first GEMM of every stage (B (1 + J) products of 8 d^3 real flops)."""
     import workloads as wl
@@ -158,6 +159,11 @@ def extras_leg(args, w, golden):
             w = wl.config_c3(batch=B, n_t=args.n_t)
         r = run_gpu(args, prec, w, golden, batch=B, steps=1, warmup=0)
         out[f"b{B}_{prec}"] = _brief(r, w)
+    # adaptive Dormand-Prince 5(4) steps with step control per problem
+    r = run_gpu(args, "f32", w, golden, batch=32, steps=1, warmup=0, adaptive=(1e-5, 1e-8))
+    b = _brief(r, w)
+    b["steps_per_slice"], b["tolerances"] = r["steps_per_slice"], r["tolerances"]
+    out["adaptive_f32"] = b
     for prec in ("f32", "f64"):
         B = 4
         r = run_gpu(args, prec, w, golden, batch=B, steps=1, warmup=0, path="dense")
@@ -187,7 +193,7 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=None, gmode=None):
+def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=None, gmode=None, adaptive=None):
     """Time `steps` gradient evaluations of the first `batch` problems of w
     (after `warmup` untimed ones); defaults from the command line."""
     import torch
@@ -202,6 +208,8 @@ def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=Non
     path = args.path if path is None else path
     gmode = args.gmode if gmode is None else gmode
     p = Problem.from_workload(w, prec=prec, path=path, gmode=gmode)
+    if adaptive:
+        p.set_adaptive(*adaptive)
     u_all = w.u.reshape(-1, n_t, w.K)
     u = torch.tensor(np.ascontiguousarray(u_all[:B]), device=dev)
     rho0 = torch.tensor(np.broadcast_to(w.rho0, (B, w.d, w.d)).copy(), device=dev)
@@ -228,10 +236,18 @@ def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=Non
     elapsed = time.perf_counter() - t0
     kern_us, kern_n = p.profile_read()
     p.profile(0)
+    stats = p.adaptive_stats(B) if adaptive else None
     phi = phi.cpu().numpy()
     g = g.cpu().numpy()
     out = dict(prec=prec, batch=B, steps=steps, elapsed=elapsed, ms_per_step=1000 * elapsed / steps,
                value=B * steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path, gradient=gmode)
+    if stats is not None:
+        out["steps_per_slice"] = {"forward_accepted": float(stats[:, 0].mean()) / n_t,
+                                  "forward_rejected": float(stats[:, 1].mean()) / n_t,
+                                  "adjoint_accepted": float(stats[:, 2].mean()) / n_t,
+                                  "adjoint_rejected": float(stats[:, 3].mean()) / n_t}
+        out["tolerances"] = {"rtol": adaptive[0], "atol": adaptive[1]}
+        golden = None  # the stored values are those of fixed RK4 steps
     gkey = "g_grape1" if gmode == "grape1" else "g_exact"
     if golden is not None and golden[gkey].shape[0] == n_t:
         out["err_phi"] = float(abs(phi[0] - golden["phi"]) / abs(golden["phi"]))

@@ -237,7 +237,11 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
         oh[q] = mkc<T>(fmad(coef, val[q].re, h.re), fmad(coef, val[q].im, h.im));
       } else {  // SM_FINAL
         cpx<T> dl = cscale(coef, val[q]);
-        for (int x = 0; x < nex; ++x) dl = cadd(dl, P.ex[x][e]);
+        // constant indices: a loop up to nex would index P.ex at run time
+        // and move the pointer table to scratch memory
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+          if (x < nex) dl = cadd(dl, P.ex[x][e]);
         cpx<T> h = sh[q];
         if (P.slo) {
           cpx<T> l = sl[q];
@@ -308,10 +312,13 @@ __global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, i
   coef_body(ops, d, K, u + (long)b * u_bs + (long)jslice * K, coef + (long)b * ops.nA * d);
 }
 
-template <typename T, int MODE, int NA, int ND, int NQ, bool PAD>
+template <typename T, int MODE, int NA, int ND, int NQ, bool PAD_>
 __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const ProbPtr<T>& P,
                                                 const cpx<T>* __restrict__ cb, T coef, int nex, int* status,
                                                 int I0, int J0, int d) {
+  // padding is used up to 8 diagonals; beyond, the padded loads of all
+  // taps would not fit in registers
+  constexpr bool PAD = PAD_ && NA <= 8;
   __shared__ cpx<T> cR[NA][TS];
   __shared__ cpx<T> cC[NA][TS];
   __shared__ cpx<T> dR[ND][TS];
