@@ -302,7 +302,7 @@ struct Engine : EngineBase {
   og::cpx<T>*ck_hi, *ck_lo, *sg_hi, *sg_lo;
   og::cpx<T>*Z1, *Z2, *Z3, *Zb1, *Zb2, *Zb3;
   og::cpx<T>*st_hi, *st_lo;  // substep start states (EXACT, n_sub > 1)
-  og::cpx<T>*Aj[2], *X, *W, *Wp;
+  og::cpx<T>*Aj[2], *X, *W, *Wp, *Ps;
   og::cpx<T>* acoef[2];  // banded: per-slice diagonal coefficients, per direction
   double* grad;
   double* pen;  // per-problem penalty traces Tr(A rho_n), n = 0..N_t
@@ -414,15 +414,17 @@ struct Engine : EngineBase {
   }
 
   // ----- workspace layout -----
+  static constexpr int kMaxRegions = 48;
   struct Layout {
-    size_t off[32];
+    size_t off[kMaxRegions];
     size_t total;
   };
   enum {
     L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
-    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_COEF, L_GRAD, L_PEN,
+    L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_PS, L_COEF, L_GRAD, L_PEN,
     L_DPK, L_DPY, L_DPD, L_DPP, L_DPC, L_DPCK, L_N
   };
+  static_assert(L_N <= kMaxRegions, "workspace layout has more regions than Layout holds");
 
   int stride_for(int nt) const {
     int s = ctx->opt.ckpt_stride;
@@ -460,6 +462,7 @@ struct Engine : EngineBase {
       sz[L_X] = m;
       sz[L_W] = (size_t)std::max(J, 1) * m;
       sz[L_WP] = (exact ? 4 : 1) * m;
+      sz[L_PS] = (J > 0 && J <= og::GM) ? (size_t)J * m : 0;
     } else {
       sz[L_COEF] = 2 * (size_t)b * og::MAXA * d * sizeof(og::cpx<T>);
     }
@@ -587,7 +590,32 @@ struct Engine : EngineBase {
     launch_gemm(g, gg);
     OG_CHECK_LAUNCH();
     ctx->prof_end(pidx, st);
-    if (J > 0) {
+    // sum_m (C_m Y) (gamma_m / 2 C_m^dag): one product per m into its own
+    // buffer (J times the blocks of a single product with inner size J d),
+    // summed in the epilogue; beyond GM collapse operators one product
+    // accumulates into X.
+    int np = 0;
+    if (J > 0 && J <= og::GM) {
+      og::GemmArgs<T> h{};
+      h.nm = J;
+      h.M = h.N = h.Kd = d;
+      h.alpha.re = 1;
+      for (int m = 0; m < J; ++m) {
+        h.A[m] = W + (long)m * d;
+        h.sA[m] = (long)J * E;
+        h.lda[m] = J * d;
+        h.B[m] = dv.Chat + (long)m * E;
+        h.sB[m] = 0;
+        h.ldb[m] = d;
+        h.C[m] = Ps + (long)m * E;
+        h.sC[m] = (long)J * E;
+        h.ldc[m] = d;
+      }
+      const dim3 hg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * J));
+      launch_gemm(h, hg);
+      OG_CHECK_LAUNCH();
+      np = J;
+    } else if (J > 0) {
       og::GemmArgs<T> h{};
       h.nm = 1;
       h.M = d;
@@ -608,12 +636,13 @@ struct Engine : EngineBase {
       launch_gemm(h, hg);
       OG_CHECK_LAUNCH();
     }
+    const long ps = (long)J * E;
     if (mode == og::SM_STAGE)
-      og::dense_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(X, E, io, tiles, ntile, d);
+      og::dense_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, tiles, ntile, d);
     else if (mode == og::SM_FINAL)
-      og::dense_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(X, E, io, tiles, ntile, d);
+      og::dense_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, tiles, ntile, d);
     else
-      og::dense_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(X, E, io, tiles, ntile, d);
+      og::dense_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, tiles, ntile, d);
     OG_CHECK_LAUNCH();
     return OG_OK;
   }
@@ -840,6 +869,7 @@ struct Engine : EngineBase {
     X = opt_at(L_X, !banded);
     W = opt_at(L_W, !banded);
     Wp = opt_at(L_WP, !banded);
+    Ps = opt_at(L_PS, !banded && J > 0 && J <= og::GM);
     acoef[0] = opt_at(L_COEF, banded);
     acoef[1] = banded ? acoef[0] + (size_t)b * og::MAXA * d : nullptr;
     grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);

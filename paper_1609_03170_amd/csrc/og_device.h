@@ -491,8 +491,19 @@ __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_ke
 // Dense right-hand side epilogue: L(Y) = X + X^dag with X = A Y + 1/2 sum
 // gamma C Y C^dag already formed by the GEMMs; then the Runge-Kutta stage.
 // ---------------------------------------------------------------------------
+// X of problem b is the sum of X[b] and the np partial products
+// Pp[b][m] (m < np, stride p_s per problem, d^2 per product), in that order.
+template <typename T>
+__device__ __forceinline__ cpx<T> x_sum(const cpx<T>* __restrict__ Xb, const cpx<T>* __restrict__ Pb, int np,
+                                        long e, long E) {
+  cpx<T> v = Xb[e];
+  for (int m = 0; m < np; ++m) v = cadd(v, Pb[(long)m * E + e]);
+  return v;
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restrict__ X, long x_s,
+                                                          const cpx<T>* __restrict__ Pp, long p_s, int np,
                                                           StageIO<T> io, const int2* __restrict__ tiles,
                                                           int ntile, int d) {
   __shared__ cpx<T> tT[TS][TS + 1];
@@ -503,6 +514,8 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
   const int2 tt = tiles[t];
   const int I0 = tt.x * TS, J0 = tt.y * TS;
   const cpx<T>* __restrict__ Xb = X + (long)b * x_s;
+  const cpx<T>* __restrict__ Pb = np > 0 ? Pp + (long)b * p_s : nullptr;
+  const long E = (long)d * d;
   const ProbPtr<T> P = resolve_strided(io, b);
   cpx<T> sh[4], sl[4];
   load_own<T, MODE>(P, d, I0, J0, tx, ty, sh, sl);
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
   for (int q = 0; q < 4; ++q) {
     const int r = ty + 8 * q;
     const int row = J0 + r, col = I0 + tx;
-    tT[r][tx] = (row < d && col < d) ? Xb[(long)row * d + col] : mkc<T>(0, 0);
+    tT[r][tx] = (row < d && col < d) ? x_sum(Xb, Pb, np, (long)row * d + col, E) : mkc<T>(0, 0);
   }
   __syncthreads();
   cpx<T> val[4];
@@ -518,7 +531,7 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
   for (int q = 0; q < 4; ++q) {
     const int r = ty + 8 * q;
     const int i = I0 + r, j = J0 + tx;
-    val[q] = (i < d && j < d) ? cadd(Xb[(long)i * d + j], conjg(tT[tx][r])) : mkc<T>(0, 0);
+    val[q] = (i < d && j < d) ? cadd(x_sum(Xb, Pb, np, (long)i * d + j, E), conjg(tT[tx][r])) : mkc<T>(0, 0);
   }
   stage_epilogue<T, MODE>(P, io.coef, io.nex, io.status, d, I0, J0, val, sh, sl, tile, tx, ty);
 }
