@@ -686,6 +686,7 @@ struct Engine : EngineBase {
                      const double* coefs, int accumulate) {
     if (K == 0) return OG_OK;
     const dim3 cg((unsigned)og::NCH, (unsigned)B);
+    const dim3 cg1((unsigned)(og::NCH * B));
     if (banded) {
       og::PairArgs<T> pa{};
       pa.np = np;
@@ -697,11 +698,11 @@ struct Engine : EngineBase {
         pa.coef[p] = coefs[p];
       }
       if (hband.nH <= 4)
-        og::band_contract_kernel<T, 4><<<cg, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
+        og::band_contract_kernel<T, 4><<<cg1, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
       else if (hband.nH <= 8)
-        og::band_contract_kernel<T, 8><<<cg, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
+        og::band_contract_kernel<T, 8><<<cg1, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
       else
-        og::band_contract_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
+        og::band_contract_kernel<T, og::MAXH><<<cg1, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
       OG_CHECK_LAUNCH();
       return OG_OK;
     }
@@ -1198,7 +1199,7 @@ struct Engine : EngineBase {
         ps.L[q] = sl.lam_hi;
         ps.out[q] = sl.part + (long)o.slice * og::NCH * K;
       }
-      const dim3 cg((unsigned)og::NCH, (unsigned)n);
+      const dim3 cg((unsigned)(og::NCH * n));
       if (hband.nH <= 4)
         og::band_contract_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
       else if (hband.nH <= 8)

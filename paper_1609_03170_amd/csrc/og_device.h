@@ -984,7 +984,10 @@ __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBan
                                                             double* __restrict__ part, long n_t, int jslice,
                                                             int accumulate) {
   __shared__ double sh[4][MAXK];
-  const int ch = blockIdx.x, b = blockIdx.y;
+  // grid = NCH * B; the chunks of one problem share an XCD (and its L2),
+  // since their row taps reach into each other's rows
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / NCH, ch = L - b * NCH;
   const int a0 = (int)((long)d * ch / NCH), a1 = (int)((long)d * (ch + 1) / NCH);
   double acc[MAXK];
 #pragma unroll
@@ -1008,7 +1011,10 @@ template <typename T, int NH>
 __global__ __launch_bounds__(256) void band_contract_slots_kernel(PairSlots<T> ps, double cf, HBand<T> hb, int K,
                                                                   int d) {
   __shared__ double sh[4][MAXK];
-  const int ch = blockIdx.x, b = blockIdx.y;
+  // grid = NCH * B; the chunks of one problem share an XCD (and its L2),
+  // since their row taps reach into each other's rows
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / NCH, ch = L - b * NCH;
   const int a0 = (int)((long)d * ch / NCH), a1 = (int)((long)d * (ch + 1) / NCH);
   double acc[MAXK];
 #pragma unroll
