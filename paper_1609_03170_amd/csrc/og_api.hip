@@ -311,7 +311,9 @@ struct Engine : EngineBase {
 
   // Dense GEMMs: float32/float64 matrix-core GEMM, or for the split
   // precisions the 16-bit three-product split GEMM (float32 storage).
+  // One launch of up to GM products (GemmArgs holds GM operand sets).
   void launch_gemm(const og::GemmArgs<T>& g, dim3 grid) {
+    if (g.nm < 1 || g.nm > og::GM) return;  // callers split larger sets (launch_gemm_set)
     if constexpr (sizeof(T) == 4) {
       if (ctx->opt.prec == OG_F32_SPLIT_BF16) {
         og::zgemm_split_kernel<og::SPLIT_BF16><<<grid, 256, 0, st>>>(g);
@@ -557,38 +559,32 @@ struct Engine : EngineBase {
       ctx->prof_end(pidx, st);
       return OG_OK;
     }
-    // dense: X = A_j in + 1/2 sum gamma C (C in)^dag ... via two GEMMs, then X + X^dag
+    // dense: X = A_j in + 1/2 sum gamma C (C in)^dag ... via two GEMMs, then X + X^dag.
+    // First the 1 + J products A_j Y and C_m Y, in launches of at most GM
+    // operand sets.
     const DirDev<T>& dv = dir[dr];
-    og::GemmArgs<T> g{};
-    g.nm = 1 + J;
-    g.M = g.N = g.Kd = d;
-    g.alpha.re = 1;
-    g.alpha.im = 0;
-    g.beta.re = 0;
-    g.beta.im = 0;
-    g.A[0] = Aj[dr];
-    g.sA[0] = E;
-    g.lda[0] = d;
-    g.C[0] = X;
-    g.sC[0] = E;
-    g.ldc[0] = d;
-    for (int m = 1; m <= J; ++m) {
-      g.A[m] = dv.C + (long)(m - 1) * E;
-      g.sA[m] = 0;
-      g.lda[m] = d;
-      g.C[m] = W + (long)(m - 1) * d;
-      g.sC[m] = (long)J * E;
-      g.ldc[m] = J * d;
-    }
-    for (int m = 0; m <= J; ++m) {
-      g.B[m] = in;
-      g.sB[m] = E;
-      g.ldb[m] = d;
-    }
-    const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * g.nm));
     const long pidx = ctx->prof_begin(st);
-    launch_gemm(g, gg);
-    OG_CHECK_LAUNCH();
+    for (int m0 = 0; m0 <= J; m0 += og::GM) {
+      og::GemmArgs<T> g{};
+      g.nm = std::min(og::GM, J + 1 - m0);
+      g.M = g.N = g.Kd = d;
+      g.alpha.re = 1;
+      for (int q = 0; q < g.nm; ++q) {
+        const int m = m0 + q;  // 0: A_j Y; m >= 1: C_m Y into column block m - 1 of W
+        g.A[q] = m == 0 ? Aj[dr] : dv.C + (long)(m - 1) * E;
+        g.sA[q] = m == 0 ? E : 0;
+        g.lda[q] = d;
+        g.C[q] = m == 0 ? X : W + (long)(m - 1) * d;
+        g.sC[q] = m == 0 ? E : (long)J * E;
+        g.ldc[q] = m == 0 ? d : J * d;
+        g.B[q] = in;
+        g.sB[q] = E;
+        g.ldb[q] = d;
+      }
+      const dim3 gg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * g.nm));
+      launch_gemm(g, gg);
+      OG_CHECK_LAUNCH();
+    }
     ctx->prof_end(pidx, st);
     // sum_m (C_m Y) (gamma_m / 2 C_m^dag): one product per m into its own
     // buffer (J times the blocks of a single product with inner size J d),

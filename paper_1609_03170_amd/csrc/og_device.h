@@ -605,26 +605,43 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
       cr[a][c] = acc_t{0, 0, 0, 0};
       ci[a][c] = acc_t{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < Kd; k0 += BK) {
+  // the operands of the next K step are loaded into registers while the
+  // matrix cores work on the current one
+  cpx<T> va[4], vb[4];
+  auto load_step = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int r = e >> 4, kk = e & 15;
       const int gm = m0 + r, gk = k0 + kk;
-      cpx<T> v = (gm < M && gk < Kd) ? A[(long)gm * lda + gk] : mkc<T>(0, 0);
-      Ar[kk][r] = v.re;
-      Ai[kk][r] = v.im;
+      va[q] = (gm < M && gk < Kd) ? A[(long)gm * lda + gk] : mkc<T>(0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int kk = e >> 6, c = e & 63;
       const int gk = k0 + kk, gn = n0 + c;
-      cpx<T> v = (gk < Kd && gn < N) ? Bm[(long)gk * ldb + gn] : mkc<T>(0, 0);
-      Br[kk][c] = v.re;
-      Bi[kk][c] = v.im;
+      vb[q] = (gk < Kd && gn < N) ? Bm[(long)gk * ldb + gn] : mkc<T>(0, 0);
+    }
+  };
+  load_step(0);
+  for (int k0 = 0; k0 < Kd; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int r = e >> 4, kk = e & 15;
+      Ar[kk][r] = va[q].re;
+      Ai[kk][r] = va[q].im;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e >> 6, c = e & 63;
+      Br[kk][c] = vb[q].re;
+      Bi[kk][c] = vb[q].im;
     }
     __syncthreads();
+    if (k0 + BK < Kd) load_step(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -737,14 +754,24 @@ __global__ __launch_bounds__(256) void zgemm_split_kernel(GemmArgs<float> g) {
   // loaders: A rows (tid / 4) with 8 consecutive k; B column (tid % 64) with 8 consecutive k
   const int arow = tid >> 2, akc = (tid & 3) * 8;
   const int bcol = tid & 63, bkc = (tid >> 6) * 8;
+  // raw operands of the next K step, loaded while the current one computes
+  cpx<float> xa[8], xb[8];
+  auto load_step = [&](int k0) {
+    const int gm = m0 + arow, gn = n0 + bcol;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int ga = k0 + akc + v, gb = k0 + bkc + v;
+      xa[v] = (gm < M && ga < Kd) ? A[(long)gm * lda + ga] : mkc<float>(0, 0);
+      xb[v] = (gb < Kd && gn < N) ? Bm[(long)gb * ldb + gn] : mkc<float>(0, 0);
+    }
+  };
+  load_step(0);
   for (int k0 = 0; k0 < Kd; k0 += BK) {
     {
       v8 p0, p1, p2, p3;
-      const int gm = m0 + arow;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const int gk = k0 + akc + v;
-        const cpx<float> x = (gm < M && gk < Kd) ? A[(long)gm * lda + gk] : mkc<float>(0, 0);
+        const cpx<float> x = xa[v];
         const float xr = x.re * sc, xi = x.im * sc;
         const e_t hr = S::cvt(xr), hi_ = S::cvt(xi);
         p0[v] = hr;
@@ -759,11 +786,9 @@ __global__ __launch_bounds__(256) void zgemm_split_kernel(GemmArgs<float> g) {
     }
     {
       v8 p0, p1, p2, p3;
-      const int gn = n0 + bcol;
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        const int gk = k0 + bkc + v;
-        const cpx<float> x = (gk < Kd && gn < N) ? Bm[(long)gk * ldb + gn] : mkc<float>(0, 0);
+        const cpx<float> x = xb[v];
         const float xr = x.re * sc, xi = x.im * sc;
         const e_t hr = S::cvt(xr), hi_ = S::cvt(xi);
         p0[v] = hr;
@@ -777,6 +802,7 @@ __global__ __launch_bounds__(256) void zgemm_split_kernel(GemmArgs<float> g) {
       *reinterpret_cast<v8*>(&Bs[3][bcol][bkc]) = p3;
     }
     __syncthreads();
+    if (k0 + BK < Kd) load_step(k0 + BK);
     const int kk = 8 * (lane >> 4);
     v8 a[2][4], bb[2][4];
 #pragma unroll

@@ -2,8 +2,8 @@
 
 Every number here comes from the float64 oracle (oracle/) on the seeded
 workloads (workloads/); nothing is read from the GPU library.  Run from the
-repository root:  python tests/golden/make_golden.py [c2] [c3] [c4]
-(all three when no argument is given).  The C3 case needs about 10 GB of
+repository root:  python tests/golden/make_golden.py [c2] [c3] [c4] [d4096]
+(all of them when no argument is given).  The C3 case needs about 10 GB of
 memory and tens of minutes on 8 cores.
 """
 from __future__ import annotations
@@ -59,7 +59,19 @@ def c4(n_t=1000):
                         rhoT_rows=rhoT[[0, 255, 511]].copy(), rhoT_diag=np.diag(rhoT).real.copy())
 
 
+D4096_ROWS = [0, 1, 63, 64, 65, 2047, 4095]
+
+
+def d4096():
+    """The largest dimension the library accepts: a damped driven resonator
+    truncated at N = 4096 (coherent amplitude 8), two slices of 2e-4."""
+    w = wl.resonator_problem(4096, 0.5, 1.0, 8.0, wl.controls_uniform(61, 2, 2), 2e-4, name="resonator4096")
+    phi, g1, _, rhoT = _run(w, w.u, sparse=True, exact=False)
+    np.savez_compressed(os.path.join(HERE, "resonator_d4096_nt2.npz"), phi=phi, g_grape1=g1,
+                        rhoT_rows=rhoT[D4096_ROWS].copy(), rows=np.array(D4096_ROWS))
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["c2", "c3", "c4"]
+    which = sys.argv[1:] or ["c2", "c3", "c4", "d4096"]
     for name in which:
-        {"c2": c2, "c3": c3, "c4": c4}[name]()
+        {"c2": c2, "c3": c3, "c4": c4, "d4096": d4096}[name]()
