@@ -7,11 +7,14 @@ room for it; every admitted request then advances together with the others
 of its shape in the batched launches of og_server_step, so requests that
 arrive while others run overlap with them on the device.  Completion time
 is taken after the stream work of the step that retired the request has
-finished; latency = completion - arrival.
+finished; latency = completion - arrival.  The shapes' steps are issued
+from one host thread each (their launches go to separate streams and
+separate contexts), so the launch work of the host does not serialise them.
 """
 from __future__ import annotations
 
 import time
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -54,12 +57,18 @@ class ServingLoop:
             self.sigma[key] = torch.tensor(w.sigma, device=self.device)
             self.rho0[key] = torch.tensor(w.rho0, device=self.device)
         self.dt = {key: w.dt for key, w in models.items()}
+        self._pool = ThreadPoolExecutor(max_workers=max(1, len(models)))
 
     def close(self):
+        self._pool.shutdown(wait=True)
         for s in self.servers.values():
             s.close()
         for p in self.problems.values():
             p.close()
+
+    def _step(self, key):
+        with torch.cuda.device(self.device), torch.cuda.stream(self.streams[key]):
+            self.servers[key].step(self.max_slices)
 
     def run(self, requests, controls, *, time_scale=1.0, keep=False, log=None):
         """requests: list of dicts with keys id, shape, arrival (seconds,
@@ -93,10 +102,8 @@ class ServingLoop:
                 if i < n_total:
                     time.sleep(max(0.0, pending[i]["arrival"] * time_scale - (time.perf_counter() - t0)))
                 continue
-            for key, srv in self.servers.items():
-                if srv.active:
-                    with torch.cuda.stream(self.streams[key]):
-                        srv.step(self.max_slices)
+            active = [key for key, srv in self.servers.items() if srv.active]
+            list(self._pool.map(self._step, active))
             torch.cuda.synchronize(self.device)
             out.steps += 1
             done_t = time.perf_counter() - t0
