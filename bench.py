@@ -54,6 +54,7 @@ def _parse():
                     help="requests submitted at once to measure the saturation throughput")
     ap.add_argument("--serve-loads", default="0.5,0.8,0.95", help="offered loads as fractions of saturation")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-slices", type=int, default=32, help="slices per request and server step")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
                     help="c3: the headline; c4: dense random d=512 precision comparison (own JSON line)")
@@ -106,7 +107,8 @@ def serving_leg(args):
     n_sat, n_load = args.serve_saturation, args.serve_requests
     reqs = wl.serving_requests(n_sat + n_load, seed=10, arrival_seed=9, rate=1.0)
     models = {s: wl.serving_model(s) for s in wl.SERVING_SHAPES}
-    loop = ServingLoop(models, prec="f32", budget_bytes=int(args.serve_budget_gib * 2**30), max_slices=16)
+    loop = ServingLoop(models, prec="f32", budget_bytes=int(args.serve_budget_gib * 2**30),
+                       max_slices=args.serve_slices)
     _log(f"[serve] saturation run: {n_sat} requests at t=0")
     sat = loop.run([dict(r, arrival=0.0) for r in reqs[:n_sat]], wl.serving_controls, log=_log)
     thr = sat.throughput()
