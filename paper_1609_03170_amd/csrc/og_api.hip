@@ -149,6 +149,45 @@ std::vector<cd> dia_values(const Mat& m, const std::vector<int>& offs, cd scale 
   return v;
 }
 
+// Ladder order of the banded taps: diagonals 0, +1, -1 first, then the
+// others; dissipator taps (0, 0) and (s, s) with s = +1 or -1 first.  Taps
+// the operators lack enter with zero coefficients.  Applied (and *lad set)
+// only when the result holds at most 5 diagonals and 3 dissipator taps, the
+// compiled bounds of the ladder stage kernel; otherwise nothing changes.
+void ladder_order(std::vector<int>& offs, std::vector<int>& tp, std::vector<int>& tq,
+                  std::vector<std::vector<cd>>& dl, std::vector<std::vector<cd>>& dr, int d, int* lad) {
+  std::vector<int> o2{0, 1, -1};
+  for (int o : offs)
+    if (o < -1 || o > 1) o2.push_back(o);
+  if (o2.size() > 5) return;
+  int iz = -1, iu = -1;
+  for (size_t t = 0; t < tp.size(); ++t) {
+    if (iz < 0 && tp[t] == 0 && tq[t] == 0) iz = (int)t;
+    if (iu < 0 && tp[t] == tq[t] && (tp[t] == 1 || tp[t] == -1)) iu = (int)t;
+  }
+  const size_t n2 = tp.size() + (iz < 0) + (iu < 0);
+  if (n2 > 3) return;
+  const std::vector<cd> zero((size_t)d, cd(0, 0));
+  std::vector<int> p2, q2;
+  std::vector<std::vector<cd>> l2, r2;
+  auto take = [&](int t, int p, int q) {
+    p2.push_back(p);
+    q2.push_back(q);
+    l2.push_back(t >= 0 ? dl[t] : zero);
+    r2.push_back(t >= 0 ? dr[t] : zero);
+  };
+  take(iz, 0, 0);
+  take(iu, iu >= 0 ? tp[iu] : 1, iu >= 0 ? tq[iu] : 1);
+  for (size_t t = 0; t < tp.size(); ++t)
+    if ((int)t != iz && (int)t != iu) take((int)t, tp[t], tq[t]);
+  offs = o2;
+  tp = p2;
+  tq = q2;
+  dl = l2;
+  dr = r2;
+  *lad = 1;
+}
+
 // Upload a host complex128 vector converted to the working precision.
 template <typename T>
 og_status upload(const std::vector<cd>& h, og::cpx<T>** dptr) {
@@ -355,27 +394,34 @@ struct Engine : EngineBase {
         collect_offsets(h.A0, offs);
         for (auto& m : h.Ak) collect_offsets(m, offs);
         if (offs.empty()) offs.push_back(0);
-        dv.band.nA = (int)offs.size();
-        for (size_t t = 0; t < offs.size(); ++t) dv.band.offA[t] = offs[t];
-        std::vector<std::vector<cd>> ak;
-        for (auto& m : h.Ak) ak.push_back(dia_values(m, offs));
-        OG_TRY(upload<T>(dia_values(h.A0, offs), &dv.bA0));
-        OG_TRY(upload<T>(concat(ak), &dv.bAk));
         std::vector<std::vector<cd>> dl, dr;
-        int nD = 0;
+        std::vector<int> tp, tq;
         for (size_t m = 0; m < h.C.size(); ++m) {
           if (h.g[m] == 0.0) continue;
           std::vector<int> co;
           collect_offsets(h.C[m], co);
           for (int p : co)
             for (int q : co) {
-              dv.band.dp[nD] = p;
-              dv.band.dq[nD] = q;
+              tp.push_back(p);
+              tq.push_back(q);
               std::vector<int> one_p{p}, one_q{q};
               dl.push_back(dia_values(h.C[m], one_p, cd(h.g[m], 0)));
               dr.push_back(dia_values(h.C[m], one_q));
-              ++nD;
             }
+        }
+        // float32 stage: ladder order when it fits the (5, 3) kernel
+        dv.band.lad = 0;
+        if (og::StageCfg<T>::PAD) ladder_order(offs, tp, tq, dl, dr, d, &dv.band.lad);
+        dv.band.nA = (int)offs.size();
+        for (size_t t = 0; t < offs.size(); ++t) dv.band.offA[t] = offs[t];
+        std::vector<std::vector<cd>> ak;
+        for (auto& m : h.Ak) ak.push_back(dia_values(m, offs));
+        OG_TRY(upload<T>(dia_values(h.A0, offs), &dv.bA0));
+        OG_TRY(upload<T>(concat(ak), &dv.bAk));
+        const int nD = (int)tp.size();
+        for (int t = 0; t < nD; ++t) {
+          dv.band.dp[t] = tp[t];
+          dv.band.dq[t] = tq[t];
         }
         dv.band.nD = nD;
         OG_TRY(upload<T>(concat(dl), &dv.bDl));
@@ -512,17 +558,19 @@ struct Engine : EngineBase {
   // resonator) or by the library maxima.  Exact-count instantiations were
   // measured slower: they hoist every tap load of the four rows of a thread
   // and fall to two waves per SIMD.
-  template <int MODE, int NA, int ND>
+  template <int MODE, int NA, int ND, bool LAD = false>
   void launch_band_v(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
-    og::band_stage_kernel<T, MODE, NA, ND><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(ops, io, tiles, ntile,
-                                                                                          d, coef);
+    og::band_stage_kernel<T, MODE, NA, ND, LAD><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(
+        ops, io, tiles, ntile, d, coef);
   }
   // compiled tap counts (NA, ND) that hold the operator: the smallest for
   // padded taps (every one is loaded), (8, 4) or more otherwise
   template <int MODE>
   void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
     const int na = ops.nA, nd = ops.nD;
-    if (og::StageCfg<T>::PAD && na <= 5 && nd <= 3)
+    if (ops.lad)  // set for the padded (float32) configuration only
+      launch_band_v<MODE, 5, 3, og::StageCfg<T>::PAD>(ops, io, coef);
+    else if (og::StageCfg<T>::PAD && na <= 5 && nd <= 3)
       launch_band_v<MODE, 5, 3>(ops, io, coef);
     else if (na <= 8 && nd <= 4)
       launch_band_v<MODE, 8, 4>(ops, io, coef);
@@ -1147,16 +1195,19 @@ struct Engine : EngineBase {
     const og::cpx<T>* pairX;
   };
 
-  template <int MODE, int NA, int ND>
+  template <int MODE, int NA, int ND, bool LAD = false>
   void launch_slots_v(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
-    og::band_stage_slots_kernel<T, MODE, NA, ND><<<dim3((unsigned)(n * ntile)), og::stage_threads<T>(), 0, st>>>(
-        dir[dr].band, tab, in_role, out_role, coef, ctx->status_dev, tiles, ntile, d);
+    og::band_stage_slots_kernel<T, MODE, NA, ND, LAD>
+        <<<dim3((unsigned)(n * ntile)), og::stage_threads<T>(), 0, st>>>(dir[dr].band, tab, in_role, out_role,
+                                                                         coef, ctx->status_dev, tiles, ntile, d);
   }
   template <int MODE>
   og_status launch_slots(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
     const og::BandOps<T>& ops = dir[dr].band;
     const long pidx = ctx->prof_begin(st);
-    if (og::StageCfg<T>::PAD && ops.nA <= 5 && ops.nD <= 3)
+    if (ops.lad)  // set for the padded (float32) configuration only
+      launch_slots_v<MODE, 5, 3, og::StageCfg<T>::PAD>(dr, tab, n, in_role, out_role, coef);
+    else if (og::StageCfg<T>::PAD && ops.nA <= 5 && ops.nD <= 3)
       launch_slots_v<MODE, 5, 3>(dr, tab, n, in_role, out_role, coef);
     else if (ops.nA <= 8 && ops.nD <= 4)
       launch_slots_v<MODE, 8, 4>(dr, tab, n, in_role, out_role, coef);

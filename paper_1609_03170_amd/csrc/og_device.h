@@ -117,6 +117,10 @@ struct BandOps {
   int dq[MAXD];
   const cpx<T>* Dl;
   const cpx<T>* Dr;
+  // ladder order: diagonals 0, +1, -1 are taps 0, 1, 2 and dissipator taps
+  // 0, 1 are (0, 0) and (s, s) with s = +-1 (read by the host to pick the
+  // stage kernel)
+  int lad;
 };
 
 // Compensated addition (hi, lo) += delta: Knuth's two-sum of hi and delta,
@@ -215,6 +219,34 @@ __device__ __forceinline__ void load_own(const ProbPtr<T>& P, int d, int I0, int
   }
 }
 
+// Runge-Kutta update of one element: out = f(coef * L, state, extras) by
+// stage mode.  exv holds the nex extra terms of the element (SM_FINAL).
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_elem(T coef, int nex, cpx<T> val, cpx<T> h, cpx<T> l, const cpx<T> (&exv)[3],
+                                           bool comp, cpx<T>& oh, cpx<T>& ol, bool& bad) {
+  if (MODE == SM_SCALE) {
+    oh = cscale(coef, val);
+  } else if (MODE == SM_STAGE) {
+    // the stage input is rounded to T anyway: the compensation term of
+    // the state changes it by at most one ulp and is not read here
+    oh = mkc<T>(fmad(coef, val.re, h.re), fmad(coef, val.im, h.im));
+  } else {  // SM_FINAL
+    cpx<T> dl = cscale(coef, val);
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+      if (x < nex) dl = cadd(dl, exv[x]);
+    if (comp) {
+      two_sum_update(h.re, l.re, dl.re);
+      two_sum_update(h.im, l.im, dl.im);
+      ol = l;
+    } else {
+      h = cadd(h, dl);
+    }
+    oh = h;
+    bad |= !(isfinite(h.re) && isfinite(h.im));
+  }
+}
+
 template <typename T, int MODE, int NQ = 4>
 __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int nex, int* status, int d, int I0,
                                                int J0, const cpx<T> (&val)[NQ], const cpx<T> (&sh)[NQ],
@@ -228,32 +260,12 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
     ol[q] = mkc<T>(0, 0);
     if (i < d && j < d) {
       const long e = (long)i * d + j;
-      if (MODE == SM_SCALE) {
-        oh[q] = cscale(coef, val[q]);
-      } else if (MODE == SM_STAGE) {
-        // the stage input is rounded to T anyway: the compensation term of
-        // the state changes it by at most one ulp and is not read here
-        const cpx<T> h = sh[q];
-        oh[q] = mkc<T>(fmad(coef, val[q].re, h.re), fmad(coef, val[q].im, h.im));
-      } else {  // SM_FINAL
-        cpx<T> dl = cscale(coef, val[q]);
-        // constant indices: a loop up to nex would index P.ex at run time
-        // and move the pointer table to scratch memory
+      cpx<T> exv[3];
+      // constant indices: a loop up to nex would index P.ex at run time
+      // and move the pointer table to scratch memory
 #pragma unroll
-        for (int x = 0; x < 3; ++x)
-          if (x < nex) dl = cadd(dl, P.ex[x][e]);
-        cpx<T> h = sh[q];
-        if (P.slo) {
-          cpx<T> l = sl[q];
-          two_sum_update(h.re, l.re, dl.re);
-          two_sum_update(h.im, l.im, dl.im);
-          ol[q] = l;
-        } else {
-          h = cadd(h, dl);
-        }
-        oh[q] = h;
-        bad |= !(isfinite(h.re) && isfinite(h.im));
-      }
+      for (int x = 0; x < 3; ++x) exv[x] = (MODE == SM_FINAL && x < nex) ? P.ex[x][e] : mkc<T>(0, 0);
+      stage_elem<T, MODE>(coef, nex, val[q], sh[q], sl[q], exv, P.slo != nullptr, oh[q], ol[q], bad);
       if (i == j) {
         oh[q].im = 0;
         ol[q].im = 0;
@@ -312,7 +324,18 @@ __global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, i
   coef_body(ops, d, K, u + (long)b * u_bs + (long)jslice * K, coef + (long)b * ops.nA * d);
 }
 
-template <typename T, int MODE, int NA, int ND, int NQ, bool PAD_>
+// Value of v held by the lane one column to the right / left in the same
+// 32-lane tile row (a lane at the row's end gets its own value back).
+template <typename T>
+__device__ __forceinline__ cpx<T> lane_next(cpx<T> v) {
+  return mkc<T>(__shfl_down(v.re, 1, TS), __shfl_down(v.im, 1, TS));
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> lane_prev(cpx<T> v) {
+  return mkc<T>(__shfl_up(v.re, 1, TS), __shfl_up(v.im, 1, TS));
+}
+
+template <typename T, int MODE, int NA, int ND, int NQ, bool PAD_, bool LAD = false>
 __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const ProbPtr<T>& P,
                                                 const cpx<T>* __restrict__ cb, T coef, int nex, int* status,
                                                 int I0, int J0, int d) {
@@ -373,15 +396,53 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
     const int ic = min(I0 + r, dm);
     const unsigned rowi = __umul24(ic, d);
     cpx<T> yr[NA], yc[NA], yd[ND];
+    if constexpr (LAD) {
+      // Ladder order: the offset-0 taps of A Y, Y A^dag and of the (0, 0)
+      // dissipator tap are the own element, loaded once; the +-1 column taps
+      // and the (s, s) dissipator tap come from the adjacent lanes' own /
+      // row-shifted elements, the lane at the tile's column edge taking the
+      // element just beyond it (one address per row).  Fewer cache lines per
+      // wave than one load per tap.
+      static_assert(NA >= 3 && ND >= 2, "ladder order needs taps 0, +1, -1 and (0, 0), (s, s)");
+      const cpx<T> y0 = ldm(Y, rowi + jc);
+      const unsigned rowp = __umul24(min(ic + 1, dm), d), rowm = __umul24(max(ic - 1, 0), d);
+      const int eR = min(J0 + TS, dm), eL = max(J0 - 1, 0);
+      yr[0] = yc[0] = yd[0] = y0;
+      yr[1] = ldm(Y, rowp + jc);
+      yr[2] = ldm(Y, rowm + jc);
+      const cpx<T> bR = ldm(Y, rowi + eR), bL = ldm(Y, rowi + eL);
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
-      if (PAD || a < nA) {
-        yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
-        yc[a] = ldm(Y, rowi + colA[a]);
+      for (int a = 3; a < NA; ++a)
+        if (PAD || a < nA) {
+          yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
+          yc[a] = ldm(Y, rowi + colA[a]);
+        }
+      const bool up = ops.dq[1] > 0;  // uniform: tap 1 is (1, 1) or (-1, -1)
+      const cpx<T> bD = ldm(Y, up ? rowp + eR : rowm + eL);
+#pragma unroll
+      for (int s = 2; s < ND; ++s)
+        if (PAD || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+      const cpx<T> n0 = lane_next(y0), p0 = lane_prev(y0);
+      yc[1] = tx == TS - 1 ? bR : n0;
+      yc[2] = tx == 0 ? bL : p0;
+      if (up) {
+        const cpx<T> v = lane_next(yr[1]);
+        yd[1] = tx == TS - 1 ? bD : v;
+      } else {
+        const cpx<T> v = lane_prev(yr[2]);
+        yd[1] = tx == 0 ? bD : v;
       }
+    } else {
 #pragma unroll
-    for (int s = 0; s < ND; ++s)
-      if (PAD || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+      for (int a = 0; a < NA; ++a)
+        if (PAD || a < nA) {
+          yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
+          yc[a] = ldm(Y, rowi + colA[a]);
+        }
+#pragma unroll
+      for (int s = 0; s < ND; ++s)
+        if (PAD || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+    }
     cpx<T> acc = mkc<T>(0, 0);
 #pragma unroll
     for (int a = 0; a < NA; ++a)
@@ -403,31 +464,37 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
 // float32 runs 512-thread blocks with every tap load in flight; float64
 // keeps 256-thread blocks whose loads stop at the operator's own taps
 // (measured faster for its twice larger registers).
+// MINW: waves per SIMD the register budget of the (5, 3) instantiations
+// must allow (two 512-thread blocks per compute unit need 4, i.e. at most
+// 128 VGPRs; the larger instantiations would spill under that bound).
 template <typename T>
 struct StageCfg {
   static constexpr int NQ = 4;
   static constexpr bool PAD = false;
+  static constexpr int MINW = 1;
 };
 template <>
 struct StageCfg<float> {
   static constexpr int NQ = 2;
   static constexpr bool PAD = true;
+  static constexpr int MINW = 4;
 };
+
 template <typename T>
 constexpr int stage_threads() {
   return TS * TS / StageCfg<T>::NQ;
 }
 
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
-template <typename T, int MODE, int NA, int ND>
-__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
+template <typename T, int MODE, int NA, int ND, bool LAD = false>
+__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ, NA <= 5 ? StageCfg<T>::MINW : 1) void band_stage_kernel(
     BandOps<T> ops, StageIO<T> io, const int2* __restrict__ tiles, int ntile, int d,
     const cpx<T>* __restrict__ coef) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   if (io.active && !io.active[b]) return;
   const int2 tt = tiles[t];
-  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD>(
+  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD, LAD>(
       ops, resolve_strided(io, b), coef + (long)b * ops.nA * d, io.coef, io.nex, io.status, tt.x * TS, tt.y * TS, d);
 }
 
@@ -467,8 +534,8 @@ __global__ __launch_bounds__(256) void band_coef_slots_kernel(BandOps<T> ops, Sl
   coef_body(ops, d, K, s.urow, s.coef);
 }
 
-template <typename T, int MODE, int NA, int ND>
-__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
+template <typename T, int MODE, int NA, int ND, bool LAD = false>
+__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ, NA <= 5 ? StageCfg<T>::MINW : 1) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
                                                                int out_role, T coef, int* status,
                                                                const int2* __restrict__ tiles, int ntile,
                                                                int d) {
@@ -483,8 +550,8 @@ __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_ke
   P.ohi = const_cast<cpx<T>*>(role_ptr(s, out_role));
   P.olo = out_role == R_OUT ? s.o_lo : nullptr;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD>(ops, P, s.coef, coef, 0, status, tt.x * TS,
-                                                                     tt.y * TS, d);
+  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD, LAD>(ops, P, s.coef, coef, 0, status,
+                                                                          tt.x * TS, tt.y * TS, d);
 }
 
 // ---------------------------------------------------------------------------
