@@ -349,11 +349,78 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   __shared__ cpx<T> tile[TS][TS + 1];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   const int nA = ops.nA, nD = ops.nD;
-  // Coefficients of the NA / ND taps; taps beyond the operator's own count
-  // get a zero coefficient (their offset is 0).  With PAD the tap loops run
-  // over all NA / ND taps without branches, so that every load of an element
-  // is issued before the arithmetic (fewer waves, more loads in flight);
-  // without PAD they stop at the operator's own counts.
+  const cpx<T>* __restrict__ Y = P.in;
+  const int dm = d - 1;
+  const int jc = min(J0 + tx, dm);
+  int colA[NA], colD[ND];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) colA[a] = clampi(jc + ops.offA[a], dm);
+#pragma unroll
+  for (int s = 0; s < ND; ++s) colD[s] = clampi(jc + ops.dq[s], dm);
+  cpx<T> val[NQ], sh[NQ], sl[NQ];
+  cpx<T> yr[NQ][NA], yc[NQ][NA], yd[NQ][ND];
+
+  // Stencil elements of row q of the thread.  With PAD the tap loops run
+  // over all NA / ND taps without branches (taps beyond the operator's own
+  // count have offset 0 and a zero coefficient); without PAD they stop at
+  // the operator's own counts.
+  auto load_taps = [&](int q) {
+    const int ic = min(I0 + ty + (TS / NQ) * q, dm);
+    const unsigned rowi = __umul24(ic, d);
+    if constexpr (LAD) {
+      // Ladder order: the offset-0 taps of A Y, Y A^dag and of the (0, 0)
+      // dissipator tap are the own element, loaded once; the +-1 column taps
+      // and the (s, s) dissipator tap come from the adjacent lanes' own /
+      // row-shifted elements, the lane at the tile's column edge taking the
+      // element just beyond it (one address per row).  Fewer cache lines per
+      // wave than one load per tap.
+      static_assert(NA >= 3 && ND >= 2, "ladder order needs taps 0, +1, -1 and (0, 0), (s, s)");
+      const cpx<T> y0 = ldm(Y, rowi + jc);
+      const unsigned rowp = __umul24(min(ic + 1, dm), d), rowm = __umul24(max(ic - 1, 0), d);
+      const int eR = min(J0 + TS, dm), eL = max(J0 - 1, 0);
+      yr[q][0] = yc[q][0] = yd[q][0] = y0;
+      yr[q][1] = ldm(Y, rowp + jc);
+      yr[q][2] = ldm(Y, rowm + jc);
+      const cpx<T> bR = ldm(Y, rowi + eR), bL = ldm(Y, rowi + eL);
+#pragma unroll
+      for (int a = 3; a < NA; ++a)
+        if (PAD || a < nA) {
+          yr[q][a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
+          yc[q][a] = ldm(Y, rowi + colA[a]);
+        }
+      const bool up = ops.dq[1] > 0;  // uniform: tap 1 is (1, 1) or (-1, -1)
+      const cpx<T> bD = ldm(Y, up ? rowp + eR : rowm + eL);
+#pragma unroll
+      for (int s = 2; s < ND; ++s)
+        if (PAD || s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+      const cpx<T> n0 = lane_next(y0), p0 = lane_prev(y0);
+      yc[q][1] = tx == TS - 1 ? bR : n0;
+      yc[q][2] = tx == 0 ? bL : p0;
+      if (up) {
+        const cpx<T> v = lane_next(yr[q][1]);
+        yd[q][1] = tx == TS - 1 ? bD : v;
+      } else {
+        const cpx<T> v = lane_prev(yr[q][2]);
+        yd[q][1] = tx == 0 ? bD : v;
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        if (PAD || a < nA) {
+          yr[q][a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
+          yc[q][a] = ldm(Y, rowi + colA[a]);
+        }
+#pragma unroll
+      for (int s = 0; s < ND; ++s)
+        if (PAD || s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+    }
+  };
+
+  // (Issuing the stencil loads before the staging barrier, so that the
+  // latencies overlap, measured slower: the coefficient loads then queue
+  // behind them.)
+  // Coefficients of the NA / ND taps for the tile's rows and columns;
+  // taps beyond the operator's own count get a zero coefficient.
   for (int e = tid; e < 2 * (NA + ND) * TS; e += TS * TS / NQ) {
     const int side = e / ((NA + ND) * TS);
     const int rem = e - side * (NA + ND) * TS;
@@ -380,79 +447,21 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
     }
   }
   __syncthreads();
-  const cpx<T>* __restrict__ Y = P.in;
-  const int dm = d - 1;
-  const int jc = min(J0 + tx, dm);
-  int colA[NA], colD[ND];
-#pragma unroll
-  for (int a = 0; a < NA; ++a) colA[a] = clampi(jc + ops.offA[a], dm);
-#pragma unroll
-  for (int s = 0; s < ND; ++s) colD[s] = clampi(jc + ops.dq[s], dm);
-  cpx<T> val[NQ], sh[NQ], sl[NQ];
-  if (PAD) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int r = ty + (TS / NQ) * q;
-    const int ic = min(I0 + r, dm);
-    const unsigned rowi = __umul24(ic, d);
-    cpx<T> yr[NA], yc[NA], yd[ND];
-    if constexpr (LAD) {
-      // Ladder order: the offset-0 taps of A Y, Y A^dag and of the (0, 0)
-      // dissipator tap are the own element, loaded once; the +-1 column taps
-      // and the (s, s) dissipator tap come from the adjacent lanes' own /
-      // row-shifted elements, the lane at the tile's column edge taking the
-      // element just beyond it (one address per row).  Fewer cache lines per
-      // wave than one load per tap.
-      static_assert(NA >= 3 && ND >= 2, "ladder order needs taps 0, +1, -1 and (0, 0), (s, s)");
-      const cpx<T> y0 = ldm(Y, rowi + jc);
-      const unsigned rowp = __umul24(min(ic + 1, dm), d), rowm = __umul24(max(ic - 1, 0), d);
-      const int eR = min(J0 + TS, dm), eL = max(J0 - 1, 0);
-      yr[0] = yc[0] = yd[0] = y0;
-      yr[1] = ldm(Y, rowp + jc);
-      yr[2] = ldm(Y, rowm + jc);
-      const cpx<T> bR = ldm(Y, rowi + eR), bL = ldm(Y, rowi + eL);
-#pragma unroll
-      for (int a = 3; a < NA; ++a)
-        if (PAD || a < nA) {
-          yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
-          yc[a] = ldm(Y, rowi + colA[a]);
-        }
-      const bool up = ops.dq[1] > 0;  // uniform: tap 1 is (1, 1) or (-1, -1)
-      const cpx<T> bD = ldm(Y, up ? rowp + eR : rowm + eL);
-#pragma unroll
-      for (int s = 2; s < ND; ++s)
-        if (PAD || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
-      const cpx<T> n0 = lane_next(y0), p0 = lane_prev(y0);
-      yc[1] = tx == TS - 1 ? bR : n0;
-      yc[2] = tx == 0 ? bL : p0;
-      if (up) {
-        const cpx<T> v = lane_next(yr[1]);
-        yd[1] = tx == TS - 1 ? bD : v;
-      } else {
-        const cpx<T> v = lane_prev(yr[2]);
-        yd[1] = tx == 0 ? bD : v;
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < NA; ++a)
-        if (PAD || a < nA) {
-          yr[a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
-          yc[a] = ldm(Y, rowi + colA[a]);
-        }
-#pragma unroll
-      for (int s = 0; s < ND; ++s)
-        if (PAD || s < nD) yd[s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
-    }
+    if (PAD && q == 0) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
+    load_taps(q);
     cpx<T> acc = mkc<T>(0, 0);
 #pragma unroll
     for (int a = 0; a < NA; ++a)
       if (PAD || a < nA) {
-        cfma(acc, cR[a][r], yr[a]);
-        cfmac(acc, yc[a], cC[a][tx]);
+        cfma(acc, cR[a][r], yr[q][a]);
+        cfmac(acc, yc[q][a], cC[a][tx]);
       }
 #pragma unroll
     for (int s = 0; s < ND; ++s)
-      if (PAD || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[s]);
+      if (PAD || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[q][s]);
     val[q] = acc;
   }
   if (!PAD) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
