@@ -409,9 +409,9 @@ struct Engine : EngineBase {
               dr.push_back(dia_values(h.C[m], one_q));
             }
         }
-        // float32 stage: ladder order when it fits the (5, 3) kernel
+        // ladder order when it fits the (5, 3) ladder kernel
         dv.band.lad = 0;
-        if (og::StageCfg<T>::PAD) ladder_order(offs, tp, tq, dl, dr, d, &dv.band.lad);
+        ladder_order(offs, tp, tq, dl, dr, d, &dv.band.lad);
         dv.band.nA = (int)offs.size();
         for (size_t t = 0; t < offs.size(); ++t) dv.band.offA[t] = offs[t];
         std::vector<std::vector<cd>> ak;
@@ -568,8 +568,8 @@ struct Engine : EngineBase {
   template <int MODE>
   void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
     const int na = ops.nA, nd = ops.nD;
-    if (ops.lad)  // set for the padded (float32) configuration only
-      launch_band_v<MODE, 5, 3, og::StageCfg<T>::PAD>(ops, io, coef);
+    if (ops.lad)
+      launch_band_v<MODE, 5, 3, true>(ops, io, coef);
     else if (og::StageCfg<T>::PAD && na <= 5 && nd <= 3)
       launch_band_v<MODE, 5, 3>(ops, io, coef);
     else if (na <= 8 && nd <= 4)
@@ -1205,8 +1205,8 @@ struct Engine : EngineBase {
   og_status launch_slots(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
     const og::BandOps<T>& ops = dir[dr].band;
     const long pidx = ctx->prof_begin(st);
-    if (ops.lad)  // set for the padded (float32) configuration only
-      launch_slots_v<MODE, 5, 3, og::StageCfg<T>::PAD>(dr, tab, n, in_role, out_role, coef);
+    if (ops.lad)
+      launch_slots_v<MODE, 5, 3, true>(dr, tab, n, in_role, out_role, coef);
     else if (og::StageCfg<T>::PAD && ops.nA <= 5 && ops.nD <= 3)
       launch_slots_v<MODE, 5, 3>(dr, tab, n, in_role, out_role, coef);
     else if (ops.nA <= 8 && ops.nD <= 4)
