@@ -553,25 +553,19 @@ struct Engine : EngineBase {
   }
 
   // The stage kernel is compiled for a few upper bounds of the number of
-  // diagonals (NA) and dissipator taps (ND); pick the smallest that fits.
-  // Instantiations bounded by 8 diagonals / 4 taps (resonator, transmon x
-  // resonator) or by the library maxima.  Exact-count instantiations were
-  // measured slower: they hoist every tap load of the four rows of a thread
-  // and fall to two waves per SIMD.
+  // diagonals (NA) and dissipator taps (ND): the ladder-order kernel (5, 3)
+  // when the operators were put in that order, else 8 diagonals / 4 taps or
+  // the library maxima.
   template <int MODE, int NA, int ND, bool LAD = false>
   void launch_band_v(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
     og::band_stage_kernel<T, MODE, NA, ND, LAD><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(
         ops, io, tiles, ntile, d, coef);
   }
-  // compiled tap counts (NA, ND) that hold the operator: the smallest for
-  // padded taps (every one is loaded), (8, 4) or more otherwise
   template <int MODE>
   void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
     const int na = ops.nA, nd = ops.nD;
     if (ops.lad)
       launch_band_v<MODE, 5, 3, true>(ops, io, coef);
-    else if (og::StageCfg<T>::PAD && na <= 5 && nd <= 3)
-      launch_band_v<MODE, 5, 3>(ops, io, coef);
     else if (na <= 8 && nd <= 4)
       launch_band_v<MODE, 8, 4>(ops, io, coef);
     else
@@ -1207,8 +1201,6 @@ struct Engine : EngineBase {
     const long pidx = ctx->prof_begin(st);
     if (ops.lad)
       launch_slots_v<MODE, 5, 3, true>(dr, tab, n, in_role, out_role, coef);
-    else if (og::StageCfg<T>::PAD && ops.nA <= 5 && ops.nD <= 3)
-      launch_slots_v<MODE, 5, 3>(dr, tab, n, in_role, out_role, coef);
     else if (ops.nA <= 8 && ops.nD <= 4)
       launch_slots_v<MODE, 8, 4>(dr, tab, n, in_role, out_role, coef);
     else

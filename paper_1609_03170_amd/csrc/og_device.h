@@ -335,13 +335,10 @@ __device__ __forceinline__ cpx<T> lane_prev(cpx<T> v) {
   return mkc<T>(__shfl_up(v.re, 1, TS), __shfl_up(v.im, 1, TS));
 }
 
-template <typename T, int MODE, int NA, int ND, int NQ, bool PAD_, bool LAD = false>
+template <typename T, int MODE, int NA, int ND, int NQ, bool LAD = false>
 __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const ProbPtr<T>& P,
                                                 const cpx<T>* __restrict__ cb, T coef, int nex, int* status,
                                                 int I0, int J0, int d) {
-  // padding is used up to 8 diagonals; beyond, the padded loads of all
-  // taps would not fit in registers
-  constexpr bool PAD = PAD_ && NA <= 8;
   __shared__ cpx<T> cR[NA][TS];
   __shared__ cpx<T> cC[NA][TS];
   __shared__ cpx<T> dR[ND][TS];
@@ -360,10 +357,8 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   cpx<T> val[NQ], sh[NQ], sl[NQ];
   cpx<T> yr[NQ][NA], yc[NQ][NA], yd[NQ][ND];
 
-  // Stencil elements of row q of the thread.  With PAD the tap loops run
-  // over all NA / ND taps without branches (taps beyond the operator's own
-  // count have offset 0 and a zero coefficient); without PAD they stop at
-  // the operator's own counts.
+  // Stencil elements of row q of the thread (the tap loops stop at the
+  // operator's own counts; NA / ND bound them at compile time).
   auto load_taps = [&](int q) {
     const int ic = min(I0 + ty + (TS / NQ) * q, dm);
     const unsigned rowi = __umul24(ic, d);
@@ -384,7 +379,7 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       const cpx<T> bR = ldm(Y, rowi + eR), bL = ldm(Y, rowi + eL);
 #pragma unroll
       for (int a = 3; a < NA; ++a)
-        if (PAD || a < nA) {
+        if (a < nA) {
           yr[q][a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
           yc[q][a] = ldm(Y, rowi + colA[a]);
         }
@@ -392,7 +387,7 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       const cpx<T> bD = ldm(Y, up ? rowp + eR : rowm + eL);
 #pragma unroll
       for (int s = 2; s < ND; ++s)
-        if (PAD || s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+        if (s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
       const cpx<T> n0 = lane_next(y0), p0 = lane_prev(y0);
       yc[q][1] = tx == TS - 1 ? bR : n0;
       yc[q][2] = tx == 0 ? bL : p0;
@@ -406,13 +401,13 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
     } else {
 #pragma unroll
       for (int a = 0; a < NA; ++a)
-        if (PAD || a < nA) {
+        if (a < nA) {
           yr[q][a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
           yc[q][a] = ldm(Y, rowi + colA[a]);
         }
 #pragma unroll
       for (int s = 0; s < ND; ++s)
-        if (PAD || s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+        if (s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
     }
   };
 
@@ -450,43 +445,30 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int r = ty + (TS / NQ) * q;
-    if (PAD && q == 0) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
     load_taps(q);
     cpx<T> acc = mkc<T>(0, 0);
 #pragma unroll
     for (int a = 0; a < NA; ++a)
-      if (PAD || a < nA) {
+      if (a < nA) {
         cfma(acc, cR[a][r], yr[q][a]);
         cfmac(acc, yc[q][a], cC[a][tx]);
       }
 #pragma unroll
     for (int s = 0; s < ND; ++s)
-      if (PAD || s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[q][s]);
+      if (s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[q][s]);
     val[q] = acc;
   }
-  if (!PAD) load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
+  load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
   stage_epilogue<T, MODE, NQ>(P, coef, nex, status, d, I0, J0, val, sh, sl, tile, tx, ty);
 }
 
-// Launch shape of the banded stage per working precision: rows of the
-// tile per thread (NQ; the block has 32 * 32 / NQ threads) and padded taps.
-// float32 runs 512-thread blocks with every tap load in flight; float64
-// keeps 256-thread blocks whose loads stop at the operator's own taps
-// (measured faster for its twice larger registers).
-// MINW: waves per SIMD the register budget of the (5, 3) instantiations
-// must allow (two 512-thread blocks per compute unit need 4, i.e. at most
-// 128 VGPRs; the larger instantiations would spill under that bound).
+// Launch shape of the banded stage: rows of the tile per thread (NQ; the
+// block has 32 * 32 / NQ threads).  Four rows (256 threads) in both
+// precisions: with the ladder order it measured faster than one or two rows
+// per thread and than tap loops padded to the compiled count.
 template <typename T>
 struct StageCfg {
   static constexpr int NQ = 4;
-  static constexpr bool PAD = false;
-  static constexpr int MINW = 1;
-};
-template <>
-struct StageCfg<float> {
-  static constexpr int NQ = 2;
-  static constexpr bool PAD = true;
-  static constexpr int MINW = 4;
 };
 
 template <typename T>
@@ -496,14 +478,14 @@ constexpr int stage_threads() {
 
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
 template <typename T, int MODE, int NA, int ND, bool LAD = false>
-__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ, NA <= 5 ? StageCfg<T>::MINW : 1) void band_stage_kernel(
+__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
     BandOps<T> ops, StageIO<T> io, const int2* __restrict__ tiles, int ntile, int d,
     const cpx<T>* __restrict__ coef) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   if (io.active && !io.active[b]) return;
   const int2 tt = tiles[t];
-  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD, LAD>(
+  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, LAD>(
       ops, resolve_strided(io, b), coef + (long)b * ops.nA * d, io.coef, io.nex, io.status, tt.x * TS, tt.y * TS, d);
 }
 
@@ -544,7 +526,7 @@ __global__ __launch_bounds__(256) void band_coef_slots_kernel(BandOps<T> ops, Sl
 }
 
 template <typename T, int MODE, int NA, int ND, bool LAD = false>
-__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ, NA <= 5 ? StageCfg<T>::MINW : 1) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
+__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
                                                                int out_role, T coef, int* status,
                                                                const int2* __restrict__ tiles, int ntile,
                                                                int d) {
@@ -559,7 +541,7 @@ __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ, NA <= 5 ? StageCfg<T>::M
   P.ohi = const_cast<cpx<T>*>(role_ptr(s, out_role));
   P.olo = out_role == R_OUT ? s.o_lo : nullptr;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, StageCfg<T>::PAD, LAD>(ops, P, s.coef, coef, 0, status,
+  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, LAD>(ops, P, s.coef, coef, 0, status,
                                                                           tt.x * TS, tt.y * TS, d);
 }
 
