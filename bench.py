@@ -41,6 +41,9 @@ def _parse():
     ap.add_argument("--gmode", default="grape1", choices=["grape1", "exact"])
     ap.add_argument("--path", default="banded", choices=["banded", "dense", "auto"])
     ap.add_argument("--precisions", default="f32,f64")
+    ap.add_argument("--resident", default="auto",
+                    help="final slices whose forward states stay in HBM (no checkpoint recompute): "
+                         "'auto' = as many as fit in the free device memory, or a count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=600, help="slices of the CPU oracle sample")
     ap.add_argument("--no-extras", action="store_true",
@@ -135,7 +138,7 @@ def serving_leg(args):
 
 
 def _brief(r, w, golden_err=True):
-    keys = ("prec", "batch", "path", "gradient", "steps", "value", "ms_per_step", "kern_us")
+    keys = ("prec", "batch", "path", "gradient", "steps", "value", "ms_per_step", "kern_us", "resident_slices")
     out = {k: r[k] for k in keys if k in r}
     out["ms_per_grad_eval"] = r["ms_per_step"] / r["batch"]
     if golden_err and "err_phi" in r:
@@ -216,8 +219,18 @@ def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=Non
     u = torch.tensor(np.ascontiguousarray(u_all[:B]), device=dev)
     rho0 = torch.tensor(np.broadcast_to(w.rho0, (B, w.d, w.d)).copy(), device=dev)
     sigma = torch.tensor(w.sigma, device=dev)
+    resident = 0
+    if not adaptive:
+        if args.resident == "auto":
+            torch.cuda.empty_cache()
+            free, total = torch.cuda.mem_get_info(dev)
+            budget = free - max(4 << 30, int(0.03 * total))  # headroom for the rest of the process
+            resident = p.resident_for_budget(B, n_t, budget)
+        else:
+            resident = min(int(args.resident), n_t)
+        p.set_resident(resident)
     ws = torch.empty(p.workspace_bytes(B, n_t), dtype=torch.uint8, device=dev)
-    _log(f"[bench] {prec} B={B} N_t={n_t} path={p.path} workspace={ws.numel() / 2**30:.2f} GiB")
+    _log(f"[bench] {prec} B={B} N_t={n_t} path={p.path} resident={resident} workspace={ws.numel() / 2**30:.2f} GiB")
 
     def step():
         phi, g = p.cost_and_grad(u, rho0, sigma, w.dt, workspace=ws)
@@ -242,7 +255,8 @@ def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=Non
     phi = phi.cpu().numpy()
     g = g.cpu().numpy()
     out = dict(prec=prec, batch=B, steps=steps, elapsed=elapsed, ms_per_step=1000 * elapsed / steps,
-               value=B * steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path, gradient=gmode)
+               value=B * steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path, gradient=gmode,
+               resident_slices=resident, workspace_gib=ws.numel() / 2**30)
     if stats is not None:
         out["steps_per_slice"] = {"forward_accepted": float(stats[:, 0].mean()) / n_t,
                                   "forward_rejected": float(stats[:, 1].mean()) / n_t,
@@ -412,7 +426,9 @@ def main():
         "config": {
             "workload": "transmon(3)xresonator(80) d=240, K=4, J=3, N_t=10000, dt=0.002/kappa, smooth-noise controls",
             "batch": args.batch, "n_t": args.n_t, "path": head["path"], "gradient": args.gmode,
-            "ckpt_stride": int(math.ceil(math.sqrt(args.n_t))), "parallelism": "none (1 GPU)",
+            "resident_slices": head["resident_slices"],
+            "ckpt_stride": int(math.ceil(math.sqrt(max(args.n_t - head["resident_slices"], 1)))),
+            "workspace_gib": round(head["workspace_gib"], 2), "parallelism": "none (1 GPU)",
         },
         "rk_steps_per_s": head["value"] * args.n_t * 2,
         "roofline": {
@@ -441,6 +457,7 @@ def main():
     if "f64" in results and "f32" in results:
         f64 = results["f64"]
         line["fp64"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
+                        "resident_slices": f64["resident_slices"],
                         "err_vs_oracle": {"phi": f64.get("err_phi"), "grad": f64.get("err_grad")}}
         line["speedup_fp32_over_fp64"] = head["value"] / f64["value"]
     if not args.no_extras:

@@ -167,6 +167,22 @@ og_status og_create_banded(og_ctx **out, int d, int K, int J, int n_diag, const 
 og_status og_set_adaptive(og_ctx *ctx, double rtol, double atol);
 
 /*
+ * Resident final states (device memory for recomputation, the trade-off of
+ * the checkpointed backward sweep that stores the forward states rho_j the
+ * gradient of Eq. (13) needs): the last n_slices slices of the forward sweep
+ * keep their states in the workspace, so that the backward sweep recomputes
+ * only the slices before them from checkpoints (every ckpt_stride slices of
+ * those, default ceil(sqrt(N_t - n_slices))).  n_slices = 0 (the default)
+ * keeps none; values above N_t keep all.  og_workspace_bytes grows by
+ * (min(n_slices, N_t) + 1) state matrices per problem (working precision,
+ * no compensation term); query it after this call.  Results are bitwise
+ * those without resident states.  Used with fixed steps, and for
+ * OG_GRAD_EXACT only with n_sub = 1 (ignored otherwise); servers refuse
+ * requests while it is set.  OG_ERR_ARG for n_slices < 0 or a NULL ctx.
+ */
+og_status og_set_resident(og_ctx *ctx, int n_slices);
+
+/*
  * Step counts of the last evaluation, per problem: counts (host, long
  * B x 4) = [accepted forward, rejected forward, accepted adjoint, rejected
  * adjoint] (the checkpoint recompute repeats the forward steps and is not
@@ -185,7 +201,8 @@ int og_path_used(const og_ctx *ctx);
  * Device workspace (bytes) that og_forward needs for a batch of B problems
  * of N_t slices: working stage buffers, the stored forward states every
  * ckpt_stride slices, one segment of recomputed states for the backward
- * sweep, and the float64 gradient.  Memory grows as O(sqrt(N_t) d^2) per
+ * sweep, the resident final states (og_set_resident) and the float64
+ * gradient.  Without resident states memory grows as O(sqrt(N_t) d^2) per
  * problem, not O(N_t d^2).  Returns 0 for invalid arguments.
  */
 size_t og_workspace_bytes(const og_ctx *ctx, int B, int n_t);

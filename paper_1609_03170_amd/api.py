@@ -40,6 +40,7 @@ EXPORTS = (
     "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
     "og_server_destroy", "og_status_string", "og_last_error", "og_gradient_sum", "og_set_penalty",
     "og_filter_apply", "og_filter_grad", "og_create_banded", "og_set_adaptive", "og_adaptive_stats",
+    "og_set_resident",
 )
 
 
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     lib.og_set_adaptive.restype = i
     lib.og_adaptive_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_long)]
     lib.og_adaptive_stats.restype = i
+    lib.og_set_resident.argtypes = [vp, i]
+    lib.og_set_resident.restype = i
     lib.og_filter_apply.argtypes = [i, i, i, i, d, d, d, vp, vp, vp]
     lib.og_filter_apply.restype = i
     lib.og_filter_grad.argtypes = [i, i, i, i, d, d, d, i, vp, vp, vp]
@@ -339,6 +342,32 @@ class Problem:
         (rtol = 0: fixed RK4 steps again).  Query workspace_bytes afterwards."""
         with torch.cuda.device(self.device):
             _check(self._lib.og_set_adaptive(self._ctx, float(rtol), float(atol)))
+
+    def set_resident(self, n_slices):
+        """Keep the states of the last n_slices slices of the forward sweep
+        in the workspace (no checkpoint recompute for them; 0: none).
+        Query workspace_bytes afterwards."""
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_set_resident(self._ctx, int(n_slices)))
+
+    def resident_for_budget(self, B, n_t, budget_bytes):
+        """Largest number of resident slices (up to n_t) whose workspace
+        fits in budget_bytes, 0 when none fits; leaves the setting at 0."""
+        def ws(r):
+            self.set_resident(r)
+            return self.workspace_bytes(B, n_t)
+        lo, hi = 0, int(n_t)
+        if ws(0) > budget_bytes:
+            lo = 0
+        else:
+            while lo < hi:  # largest r with ws(r) <= budget (ws grows with r)
+                mid = (lo + hi + 1) // 2
+                if ws(mid) <= budget_bytes:
+                    lo = mid
+                else:
+                    hi = mid - 1
+        self.set_resident(0)
+        return lo
 
     def adaptive_stats(self, B):
         """[B, 4] numpy int64: accepted / rejected steps of the forward and

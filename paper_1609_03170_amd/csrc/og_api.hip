@@ -271,6 +271,9 @@ struct og_ctx {
   int pen_nnz = 0;
   // adaptive steps (og_set_adaptive): relative / absolute tolerances, 0 = fixed steps
   double ad_rtol = 0.0, ad_atol = 0.0;
+  // og_set_resident: final slices of the forward sweep whose states stay in
+  // device memory (no checkpoint recompute for them)
+  int resident = 0;
   int* host_flag = nullptr;  // pinned: problems still active after an attempt
   // kernel timing samples (og_profile)
   int prof_every = 0;
@@ -339,6 +342,8 @@ struct Engine : EngineBase {
   // workspace views
   og::cpx<T>*cur_hi, *cur_lo, *lam_hi, *lam_lo, *Za, *Zb;
   og::cpx<T>*ck_hi, *ck_lo, *sg_hi, *sg_lo;
+  og::cpx<T>* tail = nullptr;  // resident states rho_{n_t - n_tail} .. rho_{n_t}
+  int n_tail = 0;
   og::cpx<T>*Z1, *Z2, *Z3, *Zb1, *Zb2, *Zb3;
   og::cpx<T>*st_hi, *st_lo;  // substep start states (EXACT, n_sub > 1)
   og::cpx<T>*Aj[2], *X, *W, *Wp, *Ps;
@@ -470,20 +475,32 @@ struct Engine : EngineBase {
   enum {
     L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
     L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_PS, L_COEF, L_GRAD, L_PEN,
-    L_DPK, L_DPY, L_DPD, L_DPP, L_DPC, L_DPCK, L_N
+    L_DPK, L_DPY, L_DPD, L_DPP, L_DPC, L_DPCK, L_TAIL, L_N
   };
   static_assert(L_N <= kMaxRegions, "workspace layout has more regions than Layout holds");
 
   int stride_for(int nt) const {
     int s = ctx->opt.ckpt_stride;
     if (s <= 0) s = (int)std::ceil(std::sqrt((double)nt));
-    return std::max(1, std::min(s, nt));
+    return std::max(1, std::min(s, std::max(nt, 1)));
+  }
+
+  // Resident tail: the last n_tail slices keep their states rho_j (working
+  // precision, no compensation term) from the forward sweep, so that the
+  // backward sweep recomputes only the slices before them.  Fixed steps
+  // only, and for the exact gradient one substep (whose backward pass reads
+  // no compensation term of the stored state).
+  int tail_len(int nt) const {
+    const bool ok = ctx->resident > 0 && !(ctx->ad_rtol > 0.0) &&
+                    (ctx->opt.gmode != OG_GRAD_EXACT || ctx->opt.n_sub == 1);
+    return ok ? std::min(ctx->resident, nt) : 0;
   }
 
   Layout layout(int b, int nt) const {
     Layout L{};
-    const int s = stride_for(nt);
-    const int nseg = (nt + s - 1) / s;
+    const int ntail = tail_len(nt);
+    const int s = stride_for(nt - ntail);
+    const int nseg = (nt - ntail + s - 1) / s;
     const size_t m = (size_t)b * E * sizeof(og::cpx<T>);  // one matrix per problem
     const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
     const int nsub = ctx->opt.n_sub;
@@ -525,6 +542,7 @@ struct Engine : EngineBase {
       sz[L_DPC] = kDpCtl * dpctl_bytes(b);
       sz[L_DPCK] = (size_t)nseg * b * 2 * sizeof(double);
     }
+    sz[L_TAIL] = ntail > 0 ? (size_t)(ntail + 1) * m : 0;
     size_t pos = 0;
     for (int i = 0; i < L_N; ++i) {
       L.off[i] = pos;
@@ -894,6 +912,8 @@ struct Engine : EngineBase {
     ck_lo = opt_at(L_CK_LO, comp);
     sg_hi = at(L_SG_HI);
     sg_lo = opt_at(L_SG_LO, comp);
+    n_tail = tail_len(nt);
+    tail = opt_at(L_TAIL, n_tail > 0);
     Z1 = opt_at(L_Z1, exact);
     Z2 = opt_at(L_Z2, exact);
     Z3 = opt_at(L_Z3, exact);
@@ -925,6 +945,11 @@ struct Engine : EngineBase {
     return OG_OK;
   }
 
+  og_status copy_hi(og::cpx<T>* dhi, const og::cpx<T>* shi) {
+    OG_HIP(hipMemcpyAsync(dhi, shi, (size_t)B * E * sizeof(og::cpx<T>), hipMemcpyDeviceToDevice, st));
+    return OG_OK;
+  }
+
   og_status copy_state(og::cpx<T>* dhi, og::cpx<T>* dlo, const og::cpx<T>* shi, const og::cpx<T>* slo) {
     const size_t bytes = (size_t)B * E * sizeof(og::cpx<T>);
     OG_HIP(hipMemcpyAsync(dhi, shi, bytes, hipMemcpyDeviceToDevice, st));
@@ -947,9 +972,10 @@ struct Engine : EngineBase {
     n_t = nt;
     dt = dt_;
     u = u_;
-    S = stride_for(nt);
-    n_seg = (nt + S - 1) / S;
     OG_TRY(bind(ws, b, nt));
+    const int jt = nt - n_tail;  // first slice of the resident tail
+    S = stride_for(jt);
+    n_seg = (jt + S - 1) / S;
     OG_TRY(load(rho0, E, cur_hi, cur_lo));
     OG_TRY(penalty_trace(0));
     const bool ad = ctx->ad_rtol > 0.0;
@@ -957,7 +983,7 @@ struct Engine : EngineBase {
       og::dp_init_kernel<<<1, 256, 0, st>>>(dpc[DP_FWD], B, dt);
       OG_CHECK_LAUNCH();
     }
-    for (int j = 0; j < n_t; ++j) {
+    for (int j = 0; j < jt; ++j) {
       if (j % S == 0) {
         OG_TRY(copy_state(slot(ck_hi, j / S), slot(ck_lo, j / S), cur_hi, cur_lo));
         if (ad) {
@@ -971,6 +997,16 @@ struct Engine : EngineBase {
         OG_TRY(rk_slice(FWD, j, cur_hi, cur_lo, cur_hi, cur_lo));
       OG_TRY(penalty_trace(j + 1));
     }
+    if (n_tail > 0) {
+      // the tail runs on the stored states; the compensation term stays in
+      // cur_lo (read and written at the same elements by the final stage)
+      OG_TRY(copy_hi(slot(tail, 0), cur_hi));
+      for (int k = 0; k < n_tail; ++k) {
+        OG_TRY(rk_slice(FWD, jt + k, slot(tail, k), cur_lo, slot(tail, k + 1), cur_lo));
+        OG_TRY(penalty_trace(jt + k + 1, slot(tail, k + 1)));
+      }
+      OG_TRY(copy_hi(cur_hi, slot(tail, n_tail)));
+    }
     if (rhoT) {
       const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
       og::store_state_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(cur_hi, cur_lo, E, d, static_cast<double*>(rhoT));
@@ -982,10 +1018,10 @@ struct Engine : EngineBase {
   // Penalty (Eqs. (24)-(25), App. B): Tr(A rho_n) after every slice in the
   // forward sweep, Phi -= beta dt sum_n, and lambda -= beta dt A at every
   // slice boundary of the backward sweep (the combined adjoint).
-  og_status penalty_trace(int n) {
+  og_status penalty_trace(int n, const og::cpx<T>* hi = nullptr) {
     if (ctx->pen_beta == 0.0 || !ctx->pen_coo) return OG_OK;
-    og::penalty_trace_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(ctx->pen_coo, ctx->pen_nnz, cur_hi, cur_lo, E, d,
-                                                                   pen + n, (long)n_t + 1);
+    og::penalty_trace_kernel<T><<<dim3((unsigned)B), 256, 0, st>>>(ctx->pen_coo, ctx->pen_nnz, hi ? hi : cur_hi, cur_lo,
+                                                                   E, d, pen + n, (long)n_t + 1);
     OG_CHECK_LAUNCH();
     return OG_OK;
   }
@@ -1010,9 +1046,6 @@ struct Engine : EngineBase {
 
   og_status adjoint(const void* sigma, hipStream_t s) override {
     st = s;
-    const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
-    const int nsub = ctx->opt.n_sub;
-    const T h = (T)(dt / nsub);
     OG_TRY(load(sigma, 0, lam_hi, lam_lo));
     OG_TRY(penalty_inject());
     const bool ad = ctx->ad_rtol > 0.0;
@@ -1022,8 +1055,11 @@ struct Engine : EngineBase {
       og::dp_init_kernel<<<1, 256, 0, st>>>(dpc[DP_REC], B, dt);
       OG_CHECK_LAUNCH();
     }
+    // resident tail: its states are stored, nothing to recompute
+    const int jt = n_t - n_tail;
+    for (int k = n_tail - 1; k >= 0; --k) OG_TRY(back_slice(jt + k, slot(tail, k), nullptr, slot(tail, k + 1)));
     for (int seg = n_seg - 1; seg >= 0; --seg) {
-      const int j0 = seg * S, j1 = std::min(n_t, j0 + S), n = j1 - j0;
+      const int j0 = seg * S, j1 = std::min(jt, j0 + S), n = j1 - j0;
       OG_TRY(copy_state(slot(sg_hi, 0), slot(sg_lo, 0), slot(ck_hi, seg), slot(ck_lo, seg)));
       if (ad) {
         // the recompute restarts from the controller state stored with the
@@ -1038,54 +1074,61 @@ struct Engine : EngineBase {
         for (int jj = 0; jj < n; ++jj)
           OG_TRY(rk_slice(FWD, j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1), slot(sg_lo, jj + 1)));
       }
-      for (int jj = n - 1; jj >= 0; --jj) {
-        const int j = j0 + jj;
-        if (!exact) {
-          const og::cpx<T>* Xs[1] = {slot(sg_hi, jj + 1)};
-          const og::cpx<T>* Ls[1] = {lam_hi};
-          const double cf[1] = {dt};
-          OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
-          if (ad)
-            OG_TRY(adaptive_slice(ADJ, j, lam_hi, lam_lo, dpc[DP_ADJ]));
-          else
-            OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
-          OG_TRY(penalty_inject());
-          continue;
-        }
-        // exact derivative of the RK4-discretised Phi: reverse through the
-        // nested stages Z1..Z3 of every substep of slice j.
-        OG_TRY(assemble(FWD, j));
-        OG_TRY(assemble(ADJ, j));
-        for (int sub = 1; sub < nsub; ++sub) {
-          const og::cpx<T>* phi_ = sub == 1 ? slot(sg_hi, jj) : slot(st_hi, sub - 2);
-          const og::cpx<T>* plo = sub == 1 ? slot(sg_lo, jj) : slot(st_lo, sub - 2);
-          og::cpx<T>* ohi = slot(st_hi, sub - 1);
-          og::cpx<T>* olo = slot(st_lo, sub - 1);
-          OG_TRY(stage(FWD, og::SM_STAGE, j, phi_, phi_, plo, Za, nullptr, h / T(4)));
-          OG_TRY(stage(FWD, og::SM_STAGE, j, Za, phi_, plo, Zb, nullptr, h / T(3)));
-          OG_TRY(stage(FWD, og::SM_STAGE, j, Zb, phi_, plo, Za, nullptr, h / T(2)));
-          OG_TRY(stage(FWD, og::SM_FINAL, j, Za, phi_, plo, ohi, olo, h));
-        }
-        for (int sub = nsub - 1; sub >= 0; --sub) {
-          const og::cpx<T>* s_hi = sub == 0 ? slot(sg_hi, jj) : slot(st_hi, sub - 1);
-          const og::cpx<T>* s_lo = sub == 0 ? slot(sg_lo, jj) : slot(st_lo, sub - 1);
-          OG_TRY(stage(FWD, og::SM_STAGE, j, s_hi, s_hi, s_lo, Z1, nullptr, h / T(4)));
-          OG_TRY(stage(FWD, og::SM_STAGE, j, Z1, s_hi, s_lo, Z2, nullptr, h / T(3)));
-          OG_TRY(stage(FWD, og::SM_STAGE, j, Z2, s_hi, s_lo, Z3, nullptr, h / T(2)));
-          OG_TRY(stage(ADJ, og::SM_SCALE, j, lam_hi, nullptr, nullptr, Zb3, nullptr, h));
-          OG_TRY(stage(ADJ, og::SM_SCALE, j, Zb3, nullptr, nullptr, Zb2, nullptr, h / T(2)));
-          OG_TRY(stage(ADJ, og::SM_SCALE, j, Zb2, nullptr, nullptr, Zb1, nullptr, h / T(3)));
-          const og::cpx<T>* Xs[4] = {Z3, Z2, Z1, s_hi};
-          const og::cpx<T>* Ls[4] = {lam_hi, Zb3, Zb2, Zb1};
-          const double hd = dt / nsub;
-          const double cf[4] = {hd, hd / 2, hd / 3, hd / 4};
-          OG_TRY(contract(j, 4, Xs, Ls, cf, sub != nsub - 1));
-          OG_TRY(stage(ADJ, og::SM_FINAL, j, Zb1, lam_hi, lam_lo, lam_hi, lam_lo, h / T(4), Zb1, Zb2, Zb3));
-        }
-        OG_TRY(penalty_inject());
-      }
+      for (int jj = n - 1; jj >= 0; --jj)
+        OG_TRY(back_slice(j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1)));
     }
     return OG_OK;
+  }
+
+  // One slice j of the backward sweep: the gradient contraction and the
+  // adjoint step, from rho_j (r_hi, r_lo) and rho_{j+1} (r1_hi).
+  og_status back_slice(int j, const og::cpx<T>* r_hi, const og::cpx<T>* r_lo, const og::cpx<T>* r1_hi) {
+    const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
+    const int nsub = ctx->opt.n_sub;
+    const T h = (T)(dt / nsub);
+    const bool ad = ctx->ad_rtol > 0.0;
+    if (!exact) {
+      const og::cpx<T>* Xs[1] = {r1_hi};
+      const og::cpx<T>* Ls[1] = {lam_hi};
+      const double cf[1] = {dt};
+      OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
+      if (ad)
+        OG_TRY(adaptive_slice(ADJ, j, lam_hi, lam_lo, dpc[DP_ADJ]));
+      else
+        OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
+      return penalty_inject();
+    }
+    // exact derivative of the RK4-discretised Phi: reverse through the
+    // nested stages Z1..Z3 of every substep of slice j.
+    OG_TRY(assemble(FWD, j));
+    OG_TRY(assemble(ADJ, j));
+    for (int sub = 1; sub < nsub; ++sub) {
+      const og::cpx<T>* phi_ = sub == 1 ? r_hi : slot(st_hi, sub - 2);
+      const og::cpx<T>* plo = sub == 1 ? r_lo : slot(st_lo, sub - 2);
+      og::cpx<T>* ohi = slot(st_hi, sub - 1);
+      og::cpx<T>* olo = slot(st_lo, sub - 1);
+      OG_TRY(stage(FWD, og::SM_STAGE, j, phi_, phi_, plo, Za, nullptr, h / T(4)));
+      OG_TRY(stage(FWD, og::SM_STAGE, j, Za, phi_, plo, Zb, nullptr, h / T(3)));
+      OG_TRY(stage(FWD, og::SM_STAGE, j, Zb, phi_, plo, Za, nullptr, h / T(2)));
+      OG_TRY(stage(FWD, og::SM_FINAL, j, Za, phi_, plo, ohi, olo, h));
+    }
+    for (int sub = nsub - 1; sub >= 0; --sub) {
+      const og::cpx<T>* s_hi = sub == 0 ? r_hi : slot(st_hi, sub - 1);
+      const og::cpx<T>* s_lo = sub == 0 ? r_lo : slot(st_lo, sub - 1);
+      OG_TRY(stage(FWD, og::SM_STAGE, j, s_hi, s_hi, s_lo, Z1, nullptr, h / T(4)));
+      OG_TRY(stage(FWD, og::SM_STAGE, j, Z1, s_hi, s_lo, Z2, nullptr, h / T(3)));
+      OG_TRY(stage(FWD, og::SM_STAGE, j, Z2, s_hi, s_lo, Z3, nullptr, h / T(2)));
+      OG_TRY(stage(ADJ, og::SM_SCALE, j, lam_hi, nullptr, nullptr, Zb3, nullptr, h));
+      OG_TRY(stage(ADJ, og::SM_SCALE, j, Zb3, nullptr, nullptr, Zb2, nullptr, h / T(2)));
+      OG_TRY(stage(ADJ, og::SM_SCALE, j, Zb2, nullptr, nullptr, Zb1, nullptr, h / T(3)));
+      const og::cpx<T>* Xs[4] = {Z3, Z2, Z1, s_hi};
+      const og::cpx<T>* Ls[4] = {lam_hi, Zb3, Zb2, Zb1};
+      const double hd = dt / nsub;
+      const double cf[4] = {hd, hd / 2, hd / 3, hd / 4};
+      OG_TRY(contract(j, 4, Xs, Ls, cf, sub != nsub - 1));
+      OG_TRY(stage(ADJ, og::SM_FINAL, j, Zb1, lam_hi, lam_lo, lam_hi, lam_lo, h / T(4), Zb1, Zb2, Zb3));
+    }
+    return penalty_inject();
   }
 
   og_status gradient_sum(double* out, int accumulate, hipStream_t s) override {
@@ -1132,6 +1175,7 @@ struct Engine : EngineBase {
   og_status serve_submit(const og_request& r, hipStream_t s) override {
     if (!banded) return fail(OG_ERR_SHAPE, "serving needs the banded path");
     if (ctx->ad_rtol > 0.0) return fail(OG_ERR_ARG, "serving runs fixed steps; disable adaptive steps");
+    if (ctx->resident > 0) return fail(OG_ERR_ARG, "serving keeps no resident states; og_set_resident(ctx, 0)");
     if (r.ws_bytes < ws_bytes(1, r.n_t)) return fail(OG_ERR_WORKSPACE, "request workspace too small");
     Slot sl;
     sl.r = r;
@@ -1614,6 +1658,15 @@ og_status og_set_adaptive(og_ctx* ctx, double rtol, double atol) {
   if (rtol > 0.0 && !ctx->host_flag) OG_HIP(hipHostMalloc((void**)&ctx->host_flag, sizeof(int)));
   ctx->ad_rtol = rtol;
   ctx->ad_atol = rtol > 0.0 ? atol : 0.0;
+  ctx->phase = 0;
+  return OG_OK;
+}
+
+og_status og_set_resident(og_ctx* ctx, int n_slices) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (n_slices < 0) return fail(OG_ERR_ARG, "n_slices must be >= 0");
+  ctx->resident = n_slices;
   ctx->phase = 0;
   return OG_OK;
 }

@@ -82,6 +82,7 @@ def test_host_argument_errors_without_gpu():
     assert lib.og_destroy(None) == 0
     assert lib.og_set_adaptive(None, 1e-6, 1e-8) == -1
     assert lib.og_adaptive_stats(None, None) == -1
+    assert lib.og_set_resident(None, 4) == -1
 
 
 def test_create_banded_argument_errors_without_gpu():

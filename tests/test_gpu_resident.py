@@ -1,0 +1,93 @@
+"""Resident final states (og_set_resident): the backward sweep reads the
+states of the last slices that the forward sweep kept instead of
+recomputing them from checkpoints.  Every output must equal the recompute
+path bit for bit (same kernels on the same states), for any split between
+resident and recomputed slices, with ragged segments, both gradients, both
+paths and the penalty term; the workspace follows the requested count."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from _gpu_util import TOL, gpu_eval, oracle_eval, phi_err, relerr, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(w, prec, path, gmode, resident, stride=0, penalty=None):
+    from paper_1609_03170_amd import Problem
+
+    p = Problem.from_workload(w, prec=prec, path=path, gmode=gmode, ckpt_stride=stride)
+    p.set_resident(resident)
+    if penalty is not None:
+        p.set_penalty(*penalty)
+    out = gpu_eval(w, w.u, problem=p)
+    p.close()
+    return out[:3]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("gmode", ["grape1", "exact"])
+def test_resident_tail_bitwise_banded(prec, gmode):
+    w = wl.config_c3(batch=3, n_t=23)
+    ref = _run(w, prec, "banded", gmode, 0)
+    for r, stride in ((1, 0), (5, 4), (22, 0), (23, 0), (40, 3)):
+        say(f"[case] C3-shape B=3 N_t=23 resident={r} stride={stride} {prec} {gmode}")
+        out = _run(w, prec, "banded", gmode, r, stride)
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+
+
+def test_resident_tail_matches_oracle():
+    w = wl.config_c3(batch=2, n_t=12)
+    say("[case] C3-shape B=2 N_t=12 all slices resident, float64 vs oracle")
+    phi, g, rhoT = _run(w, "f64", "banded", "grape1", 12)
+    for b in range(2):
+        phi_r, g_r, rho_r = oracle_eval(w, w.u[b])
+        tol = TOL["f64"]
+        assert phi_err(phi[b], phi_r) < tol["phi"]
+        assert relerr(g[b], g_r) < tol["grad"]
+        assert relerr(rhoT[b], rho_r) < tol["rho"]
+
+
+def test_resident_tail_bitwise_dense_and_penalty():
+    w = wl.config_c1()
+    A = np.zeros((w.d, w.d), dtype=np.complex128)
+    A[w.d - 1, w.d - 1] = 1.0  # population of the top level
+    for path in ("dense", "banded"):
+        say(f"[case] C1 resident=37 stride=5 path={path} with penalty")
+        ref = _run(w, "f32", path, "grape1", 0, penalty=(A, 0.3))
+        out = _run(w, "f32", path, "grape1", 37, stride=5, penalty=(A, 0.3))
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+
+
+def test_resident_workspace_budget_and_serving_refusal():
+    import torch
+
+    from paper_1609_03170_amd import OgError, Problem
+    from paper_1609_03170_amd.api import Server
+
+    w = wl.config_c3(batch=2, n_t=50)
+    p = Problem.from_workload(w, prec="f32")
+    w0 = p.workspace_bytes(2, 50)
+    state = 2 * w.d * w.d * 8
+    p.set_resident(50)  # all 51 states resident, no checkpoints
+    assert p.workspace_bytes(2, 50) >= 51 * state and p.workspace_bytes(2, 50) > w0
+    budget = w0 + 10 * state
+    r = p.resident_for_budget(2, 50, budget)
+    assert r >= 5
+    p.set_resident(r)
+    assert p.workspace_bytes(2, 50) <= budget
+    with pytest.raises(OgError):
+        p.set_resident(-1)
+    # serving keeps no resident states
+    p.set_resident(3)
+    srv = Server(p)
+    dev = torch.device("cuda", 0)
+    u = torch.tensor(w.u[0][:4], device=dev)
+    r0 = torch.tensor(w.rho0, device=dev)
+    sg = torch.tensor(w.sigma, device=dev)
+    with pytest.raises(OgError):
+        srv.submit(1, u, r0, sg, w.dt)
+    srv.close()
+    p.close()
