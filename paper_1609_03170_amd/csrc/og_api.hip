@@ -1236,7 +1236,7 @@ struct Engine : EngineBase {
   template <int MODE, int NA, int ND, bool LAD = false>
   void launch_slots_v(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
     og::band_stage_slots_kernel<T, MODE, NA, ND, LAD>
-        <<<dim3((unsigned)(n * ntile)), og::stage_threads<T>(), 0, st>>>(dir[dr].band, tab, in_role, out_role,
+        <<<dim3((unsigned)(n * ntile)), og::slot_threads<T>(), 0, st>>>(dir[dr].band, tab, in_role, out_role,
                                                                          coef, ctx->status_dev, tiles, ntile, d);
   }
   template <int MODE>

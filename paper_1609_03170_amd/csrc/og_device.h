@@ -476,6 +476,25 @@ constexpr int stage_threads() {
   return TS * TS / StageCfg<T>::NQ;
 }
 
+// Launch shape of the serving (slot-table) stage: one row per thread (1024
+// threads) in float32, two in float64 (whose largest instantiation would
+// spill at the 128 registers of a 1024-thread block).  Its launches hold
+// few problems (a few to a few hundred blocks) and wait on memory latency:
+// rows of one thread wait on each other's loads, so fewer rows per thread
+// measured faster there.
+template <typename T>
+struct SlotCfg {
+  static constexpr int NQ = 2;
+};
+template <>
+struct SlotCfg<float> {
+  static constexpr int NQ = 1;
+};
+template <typename T>
+constexpr int slot_threads() {
+  return TS * TS / SlotCfg<T>::NQ;
+}
+
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
 template <typename T, int MODE, int NA, int ND, bool LAD = false>
 __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
@@ -526,7 +545,7 @@ __global__ __launch_bounds__(256) void band_coef_slots_kernel(BandOps<T> ops, Sl
 }
 
 template <typename T, int MODE, int NA, int ND, bool LAD = false>
-__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
+__global__ __launch_bounds__(TS * TS / SlotCfg<T>::NQ) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
                                                                int out_role, T coef, int* status,
                                                                const int2* __restrict__ tiles, int ntile,
                                                                int d) {
@@ -541,7 +560,7 @@ __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_slots_ke
   P.ohi = const_cast<cpx<T>*>(role_ptr(s, out_role));
   P.olo = out_role == R_OUT ? s.o_lo : nullptr;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, LAD>(ops, P, s.coef, coef, 0, status,
+  band_stage_body<T, MODE, NA, ND, SlotCfg<T>::NQ, LAD>(ops, P, s.coef, coef, 0, status,
                                                                           tt.x * TS, tt.y * TS, d);
 }
 
