@@ -331,7 +331,6 @@ struct Engine : EngineBase {
   og::HBand<T> hband{};
   og::cpx<T>* hHd = nullptr;   // banded H_k diagonals
   og::cpx<T>* HT = nullptr;    // dense: transposes of H_k, K x d x d
-  int2* tiles = nullptr;
   int ntile = 0;
   static constexpr bool comp = sizeof(T) == 4;  // compensated states in float32
 
@@ -379,18 +378,12 @@ struct Engine : EngineBase {
     }
     if (hHd) (void)hipFree(hHd);
     if (HT) (void)hipFree(HT);
-    if (tiles) (void)hipFree(tiles);
   }
 
   og_status init(const DirHost host[2], const std::vector<Mat>& Hk) {
-    // upper-triangular tile list
+    // upper-triangular tiles (the kernels compute a tile's position from its index)
     const int nt = (d + og::TS - 1) / og::TS;
-    std::vector<int2> tl;
-    for (int i = 0; i < nt; ++i)
-      for (int j = i; j < nt; ++j) tl.push_back(make_int2(i, j));
-    ntile = (int)tl.size();
-    OG_HIP(hipMalloc((void**)&tiles, tl.size() * sizeof(int2)));
-    OG_HIP(hipMemcpy(tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice));
+    ntile = nt * (nt + 1) / 2;
     for (int s = 0; s < 2; ++s) {
       const DirHost& h = host[s];
       DirDev<T>& dv = dir[s];
@@ -577,7 +570,7 @@ struct Engine : EngineBase {
   template <int MODE, int NA, int ND, bool LAD = false>
   void launch_band_v(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
     og::band_stage_kernel<T, MODE, NA, ND, LAD><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(
-        ops, io, tiles, ntile, d, coef);
+        ops, io, ntile, d, coef);
   }
   template <int MODE>
   void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
@@ -694,11 +687,11 @@ struct Engine : EngineBase {
     }
     const long ps = (long)J * E;
     if (mode == og::SM_STAGE)
-      og::dense_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, tiles, ntile, d);
+      og::dense_stage_kernel<T, og::SM_STAGE><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, ntile, d);
     else if (mode == og::SM_FINAL)
-      og::dense_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, tiles, ntile, d);
+      og::dense_stage_kernel<T, og::SM_FINAL><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, ntile, d);
     else
-      og::dense_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, tiles, ntile, d);
+      og::dense_stage_kernel<T, og::SM_SCALE><<<stage_grid(), 256, 0, st>>>(X, E, Ps, ps, np, io, ntile, d);
     OG_CHECK_LAUNCH();
     return OG_OK;
   }
@@ -874,7 +867,7 @@ struct Engine : EngineBase {
       io.slo = lo;
       io.ohi = hi;
       io.olo = lo;
-      og::dp_accept_kernel<T><<<stage_grid(), 256, 0, st>>>(io, c.acc, tiles, ntile, d);
+      og::dp_accept_kernel<T><<<stage_grid(), 256, 0, st>>>(io, c.acc, ntile, d);
       OG_CHECK_LAUNCH();
       OG_HIP(hipMemcpyAsync(ctx->host_flag, c.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
       OG_HIP(hipStreamSynchronize(st));
@@ -1237,7 +1230,7 @@ struct Engine : EngineBase {
   void launch_slots_v(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {
     og::band_stage_slots_kernel<T, MODE, NA, ND, LAD>
         <<<dim3((unsigned)(n * ntile)), og::slot_threads<T>(), 0, st>>>(dir[dr].band, tab, in_role, out_role,
-                                                                         coef, ctx->status_dev, tiles, ntile, d);
+                                                                         coef, ctx->status_dev, ntile, d);
   }
   template <int MODE>
   og_status launch_slots(int dr, const og::SlotTable<T>& tab, int n, int in_role, int out_role, T coef) {

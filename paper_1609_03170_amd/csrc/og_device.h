@@ -71,6 +71,19 @@ __device__ __forceinline__ int xcd_logical_block(int id, int n) {
   return (n & 7) == 0 ? (id & 7) * (n >> 3) + (id >> 3) : id;
 }
 
+// (row, column) of the t-th upper-triangular 32 x 32 tile of a d x d matrix
+// in row-major order (tile row i holds the tiles i .. nt - 1), computed from
+// the index so that a block's first memory access is already its data.
+__device__ __forceinline__ int2 upper_tile(int t, int d) {
+  const int nt = (d + 31) / 32;
+  int i = 0;
+  while (t >= nt - i) {
+    t -= nt - i;
+    ++i;
+  }
+  return make_int2(i, i + t);
+}
+
 // ---------------------------------------------------------------------------
 // Runge-Kutta stage input / output description
 // ---------------------------------------------------------------------------
@@ -498,12 +511,11 @@ constexpr int slot_threads() {
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
 template <typename T, int MODE, int NA, int ND, bool LAD = false>
 __global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
-    BandOps<T> ops, StageIO<T> io, const int2* __restrict__ tiles, int ntile, int d,
-    const cpx<T>* __restrict__ coef) {
+    BandOps<T> ops, StageIO<T> io, int ntile, int d, const cpx<T>* __restrict__ coef) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   if (io.active && !io.active[b]) return;
-  const int2 tt = tiles[t];
+  const int2 tt = upper_tile(t, d);
   band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, LAD>(
       ops, resolve_strided(io, b), coef + (long)b * ops.nA * d, io.coef, io.nex, io.status, tt.x * TS, tt.y * TS, d);
 }
@@ -546,12 +558,11 @@ __global__ __launch_bounds__(256) void band_coef_slots_kernel(BandOps<T> ops, Sl
 
 template <typename T, int MODE, int NA, int ND, bool LAD = false>
 __global__ __launch_bounds__(TS * TS / SlotCfg<T>::NQ) void band_stage_slots_kernel(BandOps<T> ops, SlotTable<T> tab, int in_role,
-                                                               int out_role, T coef, int* status,
-                                                               const int2* __restrict__ tiles, int ntile,
+                                                               int out_role, T coef, int* status, int ntile,
                                                                int d) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
-  const int2 tt = tiles[t];
+  const int2 tt = upper_tile(t, d);
   const SlotEntry<T>& s = tab.e[b];
   ProbPtr<T> P;
   P.in = role_ptr(s, in_role);
@@ -581,14 +592,13 @@ __device__ __forceinline__ cpx<T> x_sum(const cpx<T>* __restrict__ Xb, const cpx
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restrict__ X, long x_s,
                                                           const cpx<T>* __restrict__ Pp, long p_s, int np,
-                                                          StageIO<T> io, const int2* __restrict__ tiles,
-                                                          int ntile, int d) {
+                                                          StageIO<T> io, int ntile, int d) {
   __shared__ cpx<T> tT[TS][TS + 1];
   __shared__ cpx<T> tile[TS][TS + 1];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
-  const int2 tt = tiles[t];
+  const int2 tt = upper_tile(t, d);
   const int I0 = tt.x * TS, J0 = tt.y * TS;
   const cpx<T>* __restrict__ Xb = X + (long)b * x_s;
   const cpx<T>* __restrict__ Pb = np > 0 ? Pp + (long)b * p_s : nullptr;
@@ -1521,13 +1531,13 @@ __global__ __launch_bounds__(256) void dp_control_kernel(DpCtl c, const double* 
 // compensated final-stage epilogue with coefficient 1 on the upper tiles
 // (hi mirrored, lo on the upper tiles).  grid = B * ntile.
 template <typename T>
-__global__ __launch_bounds__(256) void dp_accept_kernel(StageIO<T> io, const int* __restrict__ acc,
-                                                        const int2* __restrict__ tiles, int ntile, int d) {
+__global__ __launch_bounds__(256) void dp_accept_kernel(StageIO<T> io, const int* __restrict__ acc, int ntile,
+                                                        int d) {
   __shared__ cpx<T> tile[TS][TS + 1];
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   if (!acc[b]) return;
-  const int2 tt = tiles[t];
+  const int2 tt = upper_tile(t, d);
   const int I0 = tt.x * TS, J0 = tt.y * TS;
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   const ProbPtr<T> P = resolve_strided(io, b);
