@@ -12,6 +12,7 @@ from .cqed import (  # noqa: F401
     resonator_problem,
     transmon_resonator_problem,
     dense_random_problem,
+    banded_random_problem,
     controls_uniform,
     controls_smooth_noise,
     config_c1,

@@ -237,6 +237,58 @@ def dense_random_problem(d: int = 512, K: int = 4, J: int = 4, n_t: int = 1000, 
     return Workload(name, H0, Hk, c_ops, gammas, rho0, sigma, dt, u, meta=dict(seeds=seeds))
 
 
+def _banded(rng, d, offsets, hermitian):
+    """Random matrix whose nonzeros lie on the given diagonals (offset o:
+    entries (i, i + o)); Hermitian ones get each diagonal pair conjugate."""
+    M = np.zeros((d, d), dtype=np.complex128)
+    for o in sorted(set(offsets)):
+        if hermitian and o < 0:
+            continue
+        n = d - abs(o)
+        if n <= 0:
+            continue
+        v = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) / math.sqrt(2.0)
+        i = np.arange(n) if o >= 0 else np.arange(-o, d)
+        if hermitian and o == 0:
+            v = v.real.astype(np.complex128)
+        M[i, i + o] = v
+        if hermitian and o > 0:
+            M[i + o, i] = v.conj()
+    return M
+
+
+def banded_random_problem(d: int, h_offsets, hk_offsets, c_offsets, K: int = 2, n_t: int = 12,
+                          dt: float = 0.01, seeds=(21, 22, 23, 24, 25, 26), name: str = "banded_random") -> Workload:
+    """Operators with prescribed diagonals and random entries, for the stage
+    kernels' tap layouts: H0 Hermitian on the offsets +-h_offsets (spectral
+    norm 5), K Hermitian controls on +-hk_offsets (norm 1), one collapse
+    operator per entry of c_offsets, each on its own list of diagonals (norm
+    1, rate U[0.05, 0.2]), rho0 of rank 4, sigma Hermitian of norm 1,
+    u ~ U[-1, 1]."""
+    s_h0, s_hk, s_c, s_rho, s_sig, s_u = seeds
+    sym = lambda offs: sorted({o for x in offs for o in (x, -x)})
+    rng = np.random.default_rng(s_h0)
+    H0 = _banded(rng, d, sym(h_offsets), True)
+    H0 *= 5.0 / _spectral_norm(H0)
+    rng = np.random.default_rng(s_hk)
+    Hk = np.stack([_banded(rng, d, sym(hk_offsets), True) for _ in range(K)])
+    Hk /= np.array([_spectral_norm(h) for h in Hk])[:, None, None]
+    rng = np.random.default_rng(s_c)
+    cs = [_banded(rng, d, offs, False) for offs in c_offsets]
+    c_ops = np.stack([c / _spectral_norm(c) for c in cs])
+    gammas = rng.uniform(0.05, 0.2, size=len(cs))
+    rng = np.random.default_rng(s_rho)
+    W = (rng.standard_normal((d, 4)) + 1j * rng.standard_normal((d, 4))) / math.sqrt(2.0)
+    rho0 = W @ W.conj().T
+    rho0 /= np.trace(rho0).real
+    rng = np.random.default_rng(s_sig)
+    X = _ginibre(rng, d)
+    A = 0.5 * (X + X.conj().T)
+    sigma = A / _spectral_norm(A)
+    u = controls_uniform(s_u, n_t, K)
+    return Workload(name, H0, Hk, c_ops, gammas, rho0, sigma, dt, u, meta=dict(seeds=seeds))
+
+
 # ----------------------------------------------------------------------------
 # The five named configurations
 # ----------------------------------------------------------------------------
