@@ -91,3 +91,28 @@ def test_resident_workspace_budget_and_serving_refusal():
         srv.submit(1, u, r0, sg, w.dt)
     srv.close()
     p.close()
+
+
+def test_resident_ignored_where_not_used():
+    """Adaptive steps and the exact gradient with two substeps keep no
+    resident states: the setting changes neither the workspace nor a bit of
+    the results."""
+    from paper_1609_03170_amd import Problem
+
+    w = wl.config_c3(batch=2, n_t=9)
+    for kind in ("adaptive", "exact_nsub2"):
+        outs, sizes = [], []
+        for r in (0, 9):
+            say(f"[case] C3-shape B=2 N_t=9 {kind} resident={r}")
+            if kind == "adaptive":
+                p = Problem.from_workload(w, prec="f64", path="banded", gmode="grape1")
+                p.set_adaptive(1e-8, 1e-10)
+            else:
+                p = Problem.from_workload(w, prec="f32", path="banded", gmode="exact", n_sub=2)
+            p.set_resident(r)
+            sizes.append(p.workspace_bytes(2, 9))
+            outs.append(gpu_eval(w, w.u, problem=p)[:3])
+            p.close()
+        assert sizes[0] == sizes[1]
+        for a, b in zip(outs[0], outs[1]):
+            assert np.array_equal(a, b)
