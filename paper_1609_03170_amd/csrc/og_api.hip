@@ -346,7 +346,22 @@ struct Engine : EngineBase {
   og::cpx<T>*Z1, *Z2, *Z3, *Zb1, *Zb2, *Zb3;
   og::cpx<T>*st_hi, *st_lo;  // substep start states (EXACT, n_sub > 1)
   og::cpx<T>*Aj[2], *X, *W, *Wp, *Ps;
-  og::cpx<T>* acoef[2];  // banded: per-slice diagonal coefficients, per direction
+  // banded: diagonal coefficients of a chunk of up to kCoefChunk slices per
+  // direction, [slice - cc0[dr]][problem][diagonal][i]; a sweep refills the
+  // chunk in the order it walks the slices (coef_hint)
+  static constexpr int kCoefChunk = 64;
+  og::cpx<T>* acoef[2];
+  int cc0[2] = {0, 0}, cc1[2] = {0, 0};  // slices [cc0, cc1) held; empty when cc1 <= cc0
+  struct CoefHint {
+    int lo, hi;
+    bool asc;
+  } chint[2] = {{0, 0, true}, {0, 0, true}};
+  void coef_hint(int dr, int lo, int hi, bool asc) { chint[dr] = CoefHint{lo, hi, asc}; }
+  void coef_reset() { cc0[0] = cc1[0] = cc0[1] = cc1[1] = 0; }
+  int max_nA() const { return std::max(dir[0].band.nA, dir[1].band.nA); }
+  const og::cpx<T>* coef_ptr(int dr, int j) const {
+    return acoef[dr] + (size_t)(j - cc0[dr]) * B * dir[dr].band.nA * d;
+  }
   double* grad;
   double* pen;  // per-problem penalty traces Tr(A rho_n), n = 0..N_t
 
@@ -522,7 +537,7 @@ struct Engine : EngineBase {
       sz[L_WP] = (exact ? 4 : 1) * m;
       sz[L_PS] = (J > 0 && J <= og::GM) ? (size_t)J * m : 0;
     } else {
-      sz[L_COEF] = 2 * (size_t)b * og::MAXA * d * sizeof(og::cpx<T>);
+      sz[L_COEF] = 2 * (size_t)kCoefChunk * b * max_nA() * d * sizeof(og::cpx<T>);
     }
     // per-slice gradient partial sums, one per row chunk of the contraction
     sz[L_GRAD] = (size_t)b * nt * og::NCH * std::max(K, 1) * sizeof(double);
@@ -601,13 +616,14 @@ struct Engine : EngineBase {
     io.nex = ex2 ? 3 : (ex1 ? 2 : (ex0 ? 1 : 0));
     if (banded) {
       const og::BandOps<T>& ops = dir[dr].band;
+      OG_TRY(assemble(dr, jslice));  // no launch when slice jslice is held
       const long pidx = ctx->prof_begin(st);
       if (mode == og::SM_STAGE)
-        launch_band<og::SM_STAGE>(ops, io, acoef[dr]);
+        launch_band<og::SM_STAGE>(ops, io, coef_ptr(dr, jslice));
       else if (mode == og::SM_FINAL)
-        launch_band<og::SM_FINAL>(ops, io, acoef[dr]);
+        launch_band<og::SM_FINAL>(ops, io, coef_ptr(dr, jslice));
       else
-        launch_band<og::SM_SCALE>(ops, io, acoef[dr]);
+        launch_band<og::SM_SCALE>(ops, io, coef_ptr(dr, jslice));
       OG_CHECK_LAUNCH();
       ctx->prof_end(pidx, st);
       return OG_OK;
@@ -697,14 +713,24 @@ struct Engine : EngineBase {
   }
 
   // Slice generator assembly A(u_j) (Eq. (1)) for direction dr: diagonal
-  // coefficients (banded) or the dense matrix, for every problem.
+  // coefficients (banded) or the dense matrix, for every problem.  Banded:
+  // when slice j is not in the held chunk, the next kCoefChunk slices in the
+  // direction of the current sweep (within its range) are computed at once.
   og_status assemble(int dr, int jslice) {
     const DirDev<T>& dv = dir[dr];
     if (banded) {
+      if (jslice >= cc0[dr] && jslice < cc1[dr]) return OG_OK;
+      const CoefHint& hn = chint[dr];
+      const int lo = std::max(0, std::min(hn.lo, jslice)), hi = std::min(n_t, std::max(hn.hi, jslice + 1));
+      const int c0 = hn.asc ? jslice : std::max(lo, jslice - kCoefChunk + 1);
+      const int c1 = hn.asc ? std::min(hi, jslice + kCoefChunk) : jslice + 1;
       const int n = dv.band.nA * d;
       const unsigned gx = (unsigned)std::max(1, std::min((n + 255) / 256, 64));
-      og::band_coef_kernel<T><<<dim3(gx, (unsigned)B), 256, 0, st>>>(dv.band, d, K, u, (long)n_t * K, jslice, acoef[dr]);
+      og::band_coef_kernel<T><<<dim3(gx, (unsigned)B, (unsigned)(c1 - c0)), 256, 0, st>>>(dv.band, d, K, u, (long)n_t * K,
+                                                                                         c0, acoef[dr]);
       OG_CHECK_LAUNCH();
+      cc0[dr] = c0;
+      cc1[dr] = c1;
       return OG_OK;
     }
     const unsigned gx = (unsigned)std::min<long>((E + 255) / 256, 1024);
@@ -923,7 +949,7 @@ struct Engine : EngineBase {
     Wp = opt_at(L_WP, !banded);
     Ps = opt_at(L_PS, !banded && J > 0 && J <= og::GM);
     acoef[0] = opt_at(L_COEF, banded);
-    acoef[1] = banded ? acoef[0] + (size_t)b * og::MAXA * d : nullptr;
+    acoef[1] = banded ? acoef[0] + (size_t)kCoefChunk * b * max_nA() * d : nullptr;
     grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);
     if (ctx->ad_rtol > 0.0) {
       dpk = at(L_DPK);
@@ -966,6 +992,8 @@ struct Engine : EngineBase {
     dt = dt_;
     u = u_;
     OG_TRY(bind(ws, b, nt));
+    coef_reset();
+    coef_hint(FWD, 0, nt, true);
     const int jt = nt - n_tail;  // first slice of the resident tail
     S = stride_for(jt);
     n_seg = (jt + S - 1) / S;
@@ -1050,9 +1078,13 @@ struct Engine : EngineBase {
     }
     // resident tail: its states are stored, nothing to recompute
     const int jt = n_t - n_tail;
+    coef_reset();
+    coef_hint(ADJ, 0, n_t, false);
+    coef_hint(FWD, jt, n_t, false);
     for (int k = n_tail - 1; k >= 0; --k) OG_TRY(back_slice(jt + k, slot(tail, k), nullptr, slot(tail, k + 1)));
     for (int seg = n_seg - 1; seg >= 0; --seg) {
       const int j0 = seg * S, j1 = std::min(jt, j0 + S), n = j1 - j0;
+      coef_hint(FWD, j0, j1, true);
       OG_TRY(copy_state(slot(sg_hi, 0), slot(sg_lo, 0), slot(ck_hi, seg), slot(ck_lo, seg)));
       if (ad) {
         // the recompute restarts from the controller state stored with the
@@ -1067,6 +1099,7 @@ struct Engine : EngineBase {
         for (int jj = 0; jj < n; ++jj)
           OG_TRY(rk_slice(FWD, j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1), slot(sg_lo, jj + 1)));
       }
+      coef_hint(FWD, j0, j1, false);
       for (int jj = n - 1; jj >= 0; --jj)
         OG_TRY(back_slice(j0 + jj, slot(sg_hi, jj), slot(sg_lo, jj), slot(sg_hi, jj + 1)));
     }

@@ -329,12 +329,15 @@ __device__ __forceinline__ void coef_body(const BandOps<T>& ops, int d, int K, c
   }
 }
 
+// Coefficients of the slices jslice .. jslice + gridDim.z - 1 for every
+// problem b (gridDim.y problems): coef[z][b][a][i], nA * d per problem.
 template <typename T>
 __global__ __launch_bounds__(256) void band_coef_kernel(BandOps<T> ops, int d, int K,
                                                         const double* __restrict__ u, long u_bs, int jslice,
                                                         cpx<T>* __restrict__ coef) {
-  const int b = blockIdx.y;
-  coef_body(ops, d, K, u + (long)b * u_bs + (long)jslice * K, coef + (long)b * ops.nA * d);
+  const int b = blockIdx.y, z = blockIdx.z;
+  coef_body(ops, d, K, u + (long)b * u_bs + (long)(jslice + z) * K,
+            coef + ((long)z * gridDim.y + b) * ops.nA * d);
 }
 
 // Value of v held by the lane one column to the right / left in the same
