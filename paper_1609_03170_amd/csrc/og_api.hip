@@ -772,7 +772,9 @@ struct Engine : EngineBase {
         pa.L[p] = Ls[p];
         pa.coef[p] = coefs[p];
       }
-      if (hband.nH <= 4)
+      if (hband.nH <= 4 && K <= 4)
+        og::band_contract_kernel<T, 4, 4><<<cg1, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
+      else if (hband.nH <= 4)
         og::band_contract_kernel<T, 4><<<cg1, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);
       else if (hband.nH <= 8)
         og::band_contract_kernel<T, 8><<<cg1, 256, 0, st>>>(pa, hband, K, d, grad, n_t, jslice, accumulate);

@@ -1058,8 +1058,9 @@ __device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, cons
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nH = hb.nH, dm = d - 1;
   // CG column chunks of 64 per pass: their loads are all issued before the
-  // products (diagonals beyond nH have offset 0 and are loaded but unused)
-  constexpr int CG = 4;
+  // products (diagonals beyond nH have offset 0 and are loaded but unused).
+  // Two in float32 (fewer registers, more waves), four in float64: measured.
+  constexpr int CG = sizeof(T) == 4 ? 2 : 4;
   for (int a = a0 + wave; a < a1; a += 4) {
     // this lane's part of the row products P_t = sum_c X[a + o_t, c] conj(L[a, c])
     cpx<T> P[NH];
@@ -1095,7 +1096,9 @@ __device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, cons
   }
 }
 
-template <typename T, int NH>
+// KM bounds the number of controls K at compile time (the float64
+// accumulators of a lane; fewer registers, more waves for K <= 4).
+template <typename T, int NH, int KM = MAXK>
 __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBand<T> hb, int K, int d,
                                                             double* __restrict__ part, long n_t, int jslice,
                                                             int accumulate) {
@@ -1105,9 +1108,9 @@ __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBan
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / NCH, ch = L - b * NCH;
   const int a0 = (int)((long)d * ch / NCH), a1 = (int)((long)d * (ch + 1) / NCH);
-  double acc[MAXK];
+  double acc[KM];
 #pragma unroll
-  for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
+  for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   for (int p = 0; p < pa.np; ++p)
     contract_rows<T, NH>(pa.X[p] + (long)b * pa.x_s, pa.L[p] + (long)b * pa.l_s, pa.coef[p], hb, K, d, a0, a1,
                          acc);
