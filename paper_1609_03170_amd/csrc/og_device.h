@@ -149,25 +149,32 @@ __device__ __forceinline__ void two_sum_update(T& hi, T& lo, T delta) {
   hi = h2;
 }
 
-// Write the 32 x 32 tile held in v[NQ] (rows ty + (32/NQ) q, column tx) to out at
+// Row of the tile that value q of thread row ty holds: rows ty + (32/NQ) q
+// (strided), or with CONSEC the NQ consecutive rows NQ ty + q.
+template <int NQ, bool CONSEC>
+__device__ __forceinline__ int qrow(int ty, int q) {
+  return CONSEC ? NQ * ty + q : ty + (TS / NQ) * q;
+}
+
+// Write the 32 x 32 tile held in v[NQ] (rows qrow(ty, q), column tx) to out at
 // (I0, J0) and, with MIRROR, its conjugate transpose at (J0, I0); on a
 // diagonal tile the lower triangle is taken from the conjugated upper one.
 // Without MIRROR only the upper-triangular tiles are written: used for the
 // compensation term of the state, which is read at those tiles only (the
 // readers of whole matrices take a lower tile from its mirror).
-template <typename T, bool MIRROR = true, int NQ = 4>
+template <typename T, bool MIRROR = true, int NQ = 4, bool CONSEC = false>
 __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d, int I0, int J0,
                                                 const cpx<T> (&v)[NQ], cpx<T> (*tile)[TS + 1], int tx,
                                                 int ty) {
   constexpr int RS = TS / NQ;
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) tile[ty + RS * q][tx] = v[q];
+  for (int q = 0; q < NQ; ++q) tile[qrow<NQ, CONSEC>(ty, q)][tx] = v[q];
   __syncthreads();
   const bool diag = (I0 == J0);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int r = ty + RS * q;
+    const int r = qrow<NQ, CONSEC>(ty, q);
     const int i = I0 + r, j = J0 + tx;
     if (i < d && j < d) {
       cpx<T> z = (!diag || r <= tx) ? tile[r][tx] : conjg(tile[tx][r]);
@@ -177,7 +184,7 @@ __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d,
   if (MIRROR && !diag) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int r = ty + RS * q;
+      const int r = qrow<NQ, CONSEC>(ty, q);
       const int i = J0 + r, j = I0 + tx;
       if (i < d && j < d) out[(long)i * d + j] = conjg(tile[tx][r]);
     }
@@ -215,15 +222,15 @@ __device__ __forceinline__ ProbPtr<T> resolve_strided(const StageIO<T>& io, int 
   return P;
 }
 
-// The state elements that the epilogue adds to (rows ty + (32/NQ) q,
-// column tx of the tile), loaded by the caller together with its own loads
-// so that their latency overlaps with the right-hand side.
-template <typename T, int MODE, int NQ = 4>
+// The state elements that the epilogue adds to (rows qrow(ty, q), column tx
+// of the tile), loaded by the caller together with its own loads so that
+// their latency overlaps with the right-hand side.
+template <typename T, int MODE, int NQ = 4, bool CONSEC = false>
 __device__ __forceinline__ void load_own(const ProbPtr<T>& P, int d, int I0, int J0, int tx, int ty,
                                          cpx<T> (&sh)[NQ], cpx<T> (&sl)[NQ]) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int i = min(I0 + ty + (TS / NQ) * q, d - 1), j = min(J0 + tx, d - 1);
+    const int i = min(I0 + qrow<NQ, CONSEC>(ty, q), d - 1), j = min(J0 + tx, d - 1);
     const long e = (long)i * d + j;
     sh[q] = mkc<T>(0, 0);
     sl[q] = mkc<T>(0, 0);
@@ -260,7 +267,7 @@ __device__ __forceinline__ void stage_elem(T coef, int nex, cpx<T> val, cpx<T> h
   }
 }
 
-template <typename T, int MODE, int NQ = 4>
+template <typename T, int MODE, int NQ = 4, bool CONSEC = false>
 __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int nex, int* status, int d, int I0,
                                                int J0, const cpx<T> (&val)[NQ], const cpx<T> (&sh)[NQ],
                                                const cpx<T> (&sl)[NQ], cpx<T> (*tile)[TS + 1], int tx, int ty) {
@@ -268,7 +275,7 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
   bool bad = false;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int i = I0 + ty + (TS / NQ) * q, j = J0 + tx;
+    const int i = I0 + qrow<NQ, CONSEC>(ty, q), j = J0 + tx;
     oh[q] = mkc<T>(0, 0);
     ol[q] = mkc<T>(0, 0);
     if (i < d && j < d) {
@@ -286,8 +293,8 @@ __device__ __forceinline__ void stage_epilogue(const ProbPtr<T>& P, T coef, int 
     }
   }
   if (MODE == SM_FINAL && bad) *status = 1;
-  write_herm_tile<T, true, NQ>(P.ohi, d, I0, J0, oh, tile, tx, ty);
-  if (MODE == SM_FINAL && P.olo) write_herm_tile<T, false, NQ>(P.olo, d, I0, J0, ol, tile, tx, ty);
+  write_herm_tile<T, true, NQ, CONSEC>(P.ohi, d, I0, J0, oh, tile, tx, ty);
+  if (MODE == SM_FINAL && P.olo) write_herm_tile<T, false, NQ, CONSEC>(P.olo, d, I0, J0, ol, tile, tx, ty);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,6 +368,9 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   __shared__ cpx<T> dC[ND][TS];
   __shared__ cpx<T> tile[TS][TS + 1];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  // the ladder order holds each thread's rows consecutive (its +-1 row taps
+  // are then the neighbouring rows' own elements)
+  constexpr bool CONSEC = LAD;
   const int nA = ops.nA, nD = ops.nD;
   const cpx<T>* __restrict__ Y = P.in;
   const int dm = d - 1;
@@ -376,7 +386,7 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   // Stencil elements of row q of the thread (the tap loops stop at the
   // operator's own counts; NA / ND bound them at compile time).
   auto load_taps = [&](int q) {
-    const int ic = min(I0 + ty + (TS / NQ) * q, dm);
+    const int ic = min(I0 + qrow<NQ, CONSEC>(ty, q), dm);
     const unsigned rowi = __umul24(ic, d);
     if constexpr (LAD) {
       // Ladder order: the offset-0 taps of A Y, Y A^dag and of the (0, 0)
@@ -386,12 +396,27 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       // element just beyond it (one address per row).  Fewer cache lines per
       // wave than one load per tap.
       static_assert(NA >= 3 && ND >= 2, "ladder order needs taps 0, +1, -1 and (0, 0), (s, s)");
-      const cpx<T> y0 = ldm(Y, rowi + jc);
       const unsigned rowp = __umul24(min(ic + 1, dm), d), rowm = __umul24(max(ic - 1, 0), d);
       const int eR = min(J0 + TS, dm), eL = max(J0 - 1, 0);
-      yr[q][0] = yc[q][0] = yd[q][0] = y0;
-      yr[q][1] = ldm(Y, rowp + jc);
-      yr[q][2] = ldm(Y, rowm + jc);
+      if (CONSEC) {
+        // consecutive rows: row q + 1's own element is row q's +1 tap, row
+        // q - 1's own element its -1 tap (they differ from the clamped loads
+        // only in rows beyond the matrix, whose results are not stored)
+        if (q == 0) {
+          yr[0][0] = ldm(Y, rowi + jc);
+          yr[0][2] = ldm(Y, rowm + jc);
+        } else {
+          yr[q][2] = yr[q - 1][0];
+        }
+        yr[q][1] = ldm(Y, rowp + jc);
+        if (q + 1 < NQ) yr[q + 1][0] = yr[q][1];
+      } else {
+        yr[q][0] = ldm(Y, rowi + jc);
+        yr[q][1] = ldm(Y, rowp + jc);
+        yr[q][2] = ldm(Y, rowm + jc);
+      }
+      const cpx<T> y0 = yr[q][0];
+      yc[q][0] = yd[q][0] = y0;
       const cpx<T> bR = ldm(Y, rowi + eR), bL = ldm(Y, rowi + eL);
 #pragma unroll
       for (int a = 3; a < NA; ++a)
@@ -460,7 +485,7 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int r = ty + (TS / NQ) * q;
+    const int r = qrow<NQ, CONSEC>(ty, q);
     load_taps(q);
     cpx<T> acc = mkc<T>(0, 0);
 #pragma unroll
@@ -474,8 +499,8 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       if (s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[q][s]);
     val[q] = acc;
   }
-  load_own<T, MODE, NQ>(P, d, I0, J0, tx, ty, sh, sl);
-  stage_epilogue<T, MODE, NQ>(P, coef, nex, status, d, I0, J0, val, sh, sl, tile, tx, ty);
+  load_own<T, MODE, NQ, CONSEC>(P, d, I0, J0, tx, ty, sh, sl);
+  stage_epilogue<T, MODE, NQ, CONSEC>(P, coef, nex, status, d, I0, J0, val, sh, sl, tile, tx, ty);
 }
 
 // Launch shape of the banded stage: rows of the tile per thread (NQ; the
