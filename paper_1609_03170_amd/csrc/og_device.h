@@ -358,6 +358,19 @@ __device__ __forceinline__ cpx<T> lane_prev(cpx<T> v) {
   return mkc<T>(__shfl_up(v.re, 1, TS), __shfl_up(v.im, 1, TS));
 }
 
+// v as held by lane src of the wave (src wave-uniform): a scalar broadcast.
+template <typename T>
+__device__ __forceinline__ cpx<T> read_lane(cpx<T> v, int src) {
+  constexpr int W = (int)(sizeof(cpx<T>) / 4);
+  int w[W];
+  __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_readlane(w[i], src);
+  cpx<T> r;
+  __builtin_memcpy(&r, w, sizeof(r));
+  return r;
+}
+
 template <typename T, int MODE, int NA, int ND, int NQ, bool LAD = false>
 __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const ProbPtr<T>& P,
                                                 const cpx<T>* __restrict__ cb, T coef, int nex, int* status,
@@ -382,6 +395,13 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
   for (int s = 0; s < ND; ++s) colD[s] = clampi(jc + ops.dq[s], dm);
   cpx<T> val[NQ], sh[NQ], sl[NQ];
   cpx<T> yr[NQ][NA], yc[NQ][NA], yd[NQ][ND];
+  // ladder order with consecutive rows: the elements beyond the tile's
+  // column edges that the wave's rows need (for each half-wave, row and
+  // kind: right edge, left edge, (s, s) tap), one per lane, fetched by one
+  // load and handed out by lane reads (instead of a broadcast load each)
+  static_assert(!LAD || 6 * NQ <= 64, "edge elements of a wave exceed its lanes");
+  cpx<T> edges = mkc<T>(0, 0);
+  const int lane = tid & 63;
 
   // Stencil elements of row q of the thread (the tap loops stop at the
   // operator's own counts; NA / ND bound them at compile time).
@@ -398,11 +418,19 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       static_assert(NA >= 3 && ND >= 2, "ladder order needs taps 0, +1, -1 and (0, 0), (s, s)");
       const unsigned rowp = __umul24(min(ic + 1, dm), d), rowm = __umul24(max(ic - 1, 0), d);
       const int eR = min(J0 + TS, dm), eL = max(J0 - 1, 0);
+      const bool up = ops.dq[1] > 0;  // uniform: tap 1 is (1, 1) or (-1, -1)
       if (CONSEC) {
         // consecutive rows: row q + 1's own element is row q's +1 tap, row
         // q - 1's own element its -1 tap (they differ from the clamped loads
         // only in rows beyond the matrix, whose results are not stored)
         if (q == 0) {
+          // lane e < 6 NQ: half-wave e / (3 NQ), row (e mod 3 NQ) / 3, kind e mod 3
+          const int e = min(lane, 6 * NQ - 1);
+          const int hh = e / (3 * NQ), rr = e - hh * 3 * NQ, qq = rr / 3, kind = rr - qq * 3;
+          const int ie = min(I0 + qrow<NQ, CONSEC>(((tid >> 6) << 1) + hh, qq), dm);
+          const int re = kind == 2 ? (up ? min(ie + 1, dm) : max(ie - 1, 0)) : ie;
+          const int ce = kind == 0 || (kind == 2 && up) ? eR : eL;
+          edges = ldm(Y, __umul24(re, d) + ce);
           yr[0][0] = ldm(Y, rowi + jc);
           yr[0][2] = ldm(Y, rowm + jc);
         } else {
@@ -417,18 +445,30 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       }
       const cpx<T> y0 = yr[q][0];
       yc[q][0] = yd[q][0] = y0;
-      const cpx<T> bR = ldm(Y, rowi + eR), bL = ldm(Y, rowi + eL);
+      cpx<T> bR, bL, bD;
+      if (!CONSEC) {
+        bR = ldm(Y, rowi + eR);
+        bL = ldm(Y, rowi + eL);
+        bD = ldm(Y, up ? rowp + eR : rowm + eL);
+      }
 #pragma unroll
       for (int a = 3; a < NA; ++a)
         if (a < nA) {
           yr[q][a] = ldm(Y, __umul24(clampi(ic + ops.offA[a], dm), d) + jc);
           yc[q][a] = ldm(Y, rowi + colA[a]);
         }
-      const bool up = ops.dq[1] > 0;  // uniform: tap 1 is (1, 1) or (-1, -1)
-      const cpx<T> bD = ldm(Y, up ? rowp + eR : rowm + eL);
 #pragma unroll
       for (int s = 2; s < ND; ++s)
         if (s < nD) yd[q][s] = ldm(Y, __umul24(clampi(ic + ops.dp[s], dm), d) + colD[s]);
+      if (CONSEC) {
+        const bool h1 = lane >= 32;
+        const cpx<T> r0 = read_lane(edges, 3 * q), r1 = read_lane(edges, 3 * NQ + 3 * q);
+        const cpx<T> l0 = read_lane(edges, 3 * q + 1), l1 = read_lane(edges, 3 * NQ + 3 * q + 1);
+        const cpx<T> d0 = read_lane(edges, 3 * q + 2), d1 = read_lane(edges, 3 * NQ + 3 * q + 2);
+        bR = h1 ? r1 : r0;
+        bL = h1 ? l1 : l0;
+        bD = h1 ? d1 : d0;
+      }
       const cpx<T> n0 = lane_next(y0), p0 = lane_prev(y0);
       yc[q][1] = tx == TS - 1 ? bR : n0;
       yc[q][2] = tx == 0 ? bL : p0;
