@@ -413,8 +413,8 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       // dissipator tap are the own element, loaded once; the +-1 column taps
       // and the (s, s) dissipator tap come from the adjacent lanes' own /
       // row-shifted elements, the lane at the tile's column edge taking the
-      // element just beyond it (one address per row).  Fewer cache lines per
-      // wave than one load per tap.
+      // element just beyond it (with consecutive rows, from the wave's edge
+      // load).  Fewer load instructions than one load per tap.
       static_assert(NA >= 3 && ND >= 2, "ladder order needs taps 0, +1, -1 and (0, 0), (s, s)");
       const unsigned rowp = __umul24(min(ic + 1, dm), d), rowm = __umul24(max(ic - 1, 0), d);
       const int eR = min(J0 + TS, dm), eL = max(J0 - 1, 0);
@@ -523,6 +523,11 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
     }
   }
   __syncthreads();
+  // the state with the first row's taps (ladder order, nested stages, float32:
+  // measured faster there; the final stage keeps its registers for the
+  // compensated update, float64 its occupancy)
+  constexpr bool OWN_FIRST = LAD && MODE != SM_FINAL && sizeof(T) == 4;
+  if (OWN_FIRST) load_own<T, MODE, NQ, CONSEC>(P, d, I0, J0, tx, ty, sh, sl);
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int r = qrow<NQ, CONSEC>(ty, q);
@@ -539,7 +544,7 @@ __device__ __forceinline__ void band_stage_body(const BandOps<T>& ops, const Pro
       if (s < nD) cfma(acc, cmulc(dR[s][r], dC[s][tx]), yd[q][s]);
     val[q] = acc;
   }
-  load_own<T, MODE, NQ, CONSEC>(P, d, I0, J0, tx, ty, sh, sl);
+  if (!OWN_FIRST) load_own<T, MODE, NQ, CONSEC>(P, d, I0, J0, tx, ty, sh, sl);
   stage_epilogue<T, MODE, NQ, CONSEC>(P, coef, nex, status, d, I0, J0, val, sh, sl, tile, tx, ty);
 }
 
