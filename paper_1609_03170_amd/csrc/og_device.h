@@ -1125,7 +1125,10 @@ __device__ __forceinline__ void write_partials(double (*sh)[MAXK], const double*
 template <typename T, int NH>
 __device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, const cpx<T>* __restrict__ Lm, double cf,
                                               const HBand<T>& hb, int K, int d, int a0, int a1, double* acc) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index as a wave-uniform value: the row a and the weights
+  // H_k[a, a + o_t] of a row are then scalar, loaded together through the
+  // scalar cache instead of one vector load (and wait) each
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nH = hb.nH, dm = d - 1;
   // CG column chunks of 64 per pass: their loads are all issued before the
   // products (diagonals beyond nH have offset 0 and are loaded but unused).
