@@ -1122,7 +1122,7 @@ __device__ __forceinline__ void write_partials(double (*sh)[MAXK], const double*
 }
 
 // acc[k] += cf * 2-less Im-part sum over the rows [a0, a1) of chunk ch.
-template <typename T, int NH>
+template <typename T, int NH, int KM = MAXK>
 __device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, const cpx<T>* __restrict__ Lm, double cf,
                                               const HBand<T>& hb, int K, int d, int a0, int a1, double* acc) {
   // the wave index as a wave-uniform value: the row a and the weights
@@ -1132,8 +1132,10 @@ __device__ __forceinline__ void contract_rows(const cpx<T>* __restrict__ X, cons
   const int nH = hb.nH, dm = d - 1;
   // CG column chunks of 64 per pass: their loads are all issued before the
   // products (diagonals beyond nH have offset 0 and are loaded but unused).
-  // Two in float32 (fewer registers, more waves), four in float64: measured.
-  constexpr int CG = sizeof(T) == 4 ? 2 : 4;
+  // The widest count that keeps the most waves resident, measured: with at
+  // most 4 controls four in float32 (62 registers) and two in float64 (68),
+  // with more controls two in float32 and four in float64.
+  constexpr int CG = sizeof(T) == 8 ? (KM <= 4 ? 2 : 4) : (KM <= 4 ? 4 : 2);
   for (int a = a0 + wave; a < a1; a += 4) {
     // this lane's part of the row products P_t = sum_c X[a + o_t, c] conj(L[a, c])
     cpx<T> P[NH];
@@ -1185,8 +1187,8 @@ __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBan
 #pragma unroll
   for (int k = 0; k < KM; ++k) acc[k] = 0.0;
   for (int p = 0; p < pa.np; ++p)
-    contract_rows<T, NH>(pa.X[p] + (long)b * pa.x_s, pa.L[p] + (long)b * pa.l_s, pa.coef[p], hb, K, d, a0, a1,
-                         acc);
+    contract_rows<T, NH, KM>(pa.X[p] + (long)b * pa.x_s, pa.L[p] + (long)b * pa.l_s, pa.coef[p], hb, K, d, a0,
+                             a1, acc);
   write_partials(sh, acc, K, part, (((long)b * n_t + jslice) * NCH + ch) * K, accumulate);
 }
 
