@@ -65,8 +65,9 @@ typedef enum {
 typedef enum {
     OG_F64 = 0,                /* float64 states and arithmetic                */
     OG_F32 = 1,                /* float32 arithmetic; states carried as a
-                                  compensated (hi, lo) float32 pair; cost,
-                                  trace and gradient sums in float64          */
+                                  float32 hi part plus a compensation term
+                                  (two bfloat16 per element); cost, trace
+                                  and gradient sums in float64               */
     OG_F32_SPLIT_BF16 = 2,     /* as OG_F32, but the dense-path GEMMs split
                                   every float32 operand into two bfloat16
                                   parts and use three bfloat16 matrix-core

@@ -149,6 +149,34 @@ __device__ __forceinline__ void two_sum_update(T& hi, T& lo, T delta) {
   hi = h2;
 }
 
+// Storage of the compensation term.  In float32 it is kept as two bfloat16
+// (real part in the low half of a 32-bit word, imaginary part in the high
+// half), rounded to nearest even, at word e of the problem's buffer: 4 bytes
+// per element, so the final stage moves half the bytes of a float32 pair.
+// |lo| is at most half an ulp of hi, so the stored term still carries 8 bits
+// below the 24 of hi: a rounding error of at most 2^-33 |hi| per step instead
+// of 2^-24 |hi| without the term.  Float64 states carry no compensation term.
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> lo_ld(const cpx<T>* __restrict__ lo, long e) {
+  if constexpr (sizeof(T) == 4) {
+    const unsigned w = reinterpret_cast<const unsigned*>(lo)[e];
+    return mkc<T>(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+  } else {
+    return lo[e];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void lo_st(cpx<T>* __restrict__ lo, long e, cpx<T> v) {
+  if constexpr (sizeof(T) == 4)
+    reinterpret_cast<unsigned*>(lo)[e] = bf16_rne(v.re) | (bf16_rne(v.im) << 16);
+  else
+    lo[e] = v;
+}
+
 // Row of the tile that value q of thread row ty holds: rows ty + (32/NQ) q
 // (strided), or with CONSEC the NQ consecutive rows NQ ty + q.
 template <int NQ, bool CONSEC>
@@ -160,8 +188,9 @@ __device__ __forceinline__ int qrow(int ty, int q) {
 // (I0, J0) and, with MIRROR, its conjugate transpose at (J0, I0); on a
 // diagonal tile the lower triangle is taken from the conjugated upper one.
 // Without MIRROR only the upper-triangular tiles are written: used for the
-// compensation term of the state, which is read at those tiles only (the
-// readers of whole matrices take a lower tile from its mirror).
+// compensation term of the state (stored by lo_st), which is read at those
+// tiles only (the readers of whole matrices take a lower tile from its
+// mirror).
 template <typename T, bool MIRROR = true, int NQ = 4, bool CONSEC = false>
 __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d, int I0, int J0,
                                                 const cpx<T> (&v)[NQ], cpx<T> (*tile)[TS + 1], int tx,
@@ -178,7 +207,10 @@ __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d,
     const int i = I0 + r, j = J0 + tx;
     if (i < d && j < d) {
       cpx<T> z = (!diag || r <= tx) ? tile[r][tx] : conjg(tile[tx][r]);
-      out[(long)i * d + j] = z;
+      if (MIRROR)
+        out[(long)i * d + j] = z;
+      else
+        lo_st(out, (long)i * d + j, z);
     }
   }
   if (MIRROR && !diag) {
@@ -195,7 +227,7 @@ __device__ __forceinline__ void write_herm_tile(cpx<T>* __restrict__ out, int d,
 template <typename T>
 __device__ __forceinline__ cpx<T> lo_at(const cpx<T>* __restrict__ lo, int d, long e) {
   const int i = (int)(e / d), j = (int)(e - (long)i * d);
-  return (i / TS > j / TS) ? conjg(lo[(long)j * d + i]) : lo[e];
+  return (i / TS > j / TS) ? conjg(lo_ld(lo, (long)j * d + i)) : lo_ld(lo, e);
 }
 
 // Per-problem addresses of one stage launch.
@@ -235,7 +267,7 @@ __device__ __forceinline__ void load_own(const ProbPtr<T>& P, int d, int I0, int
     sh[q] = mkc<T>(0, 0);
     sl[q] = mkc<T>(0, 0);
     if (MODE != SM_SCALE) sh[q] = P.shi[e];
-    if (MODE == SM_FINAL && P.slo) sl[q] = P.slo[e];
+    if (MODE == SM_FINAL && P.slo) sl[q] = lo_ld(P.slo, e);
   }
 }
 
@@ -1387,7 +1419,7 @@ __global__ __launch_bounds__(256) void load_state_kernel(const double* __restric
     const double xr = src[2 * ((long)b * src_s + e)], xi = src[2 * ((long)b * src_s + e) + 1];
     const T hr = (T)xr, him = (T)xi;
     hi[(long)b * s_s + e] = mkc<T>(hr, him);
-    if (lo) lo[(long)b * s_s + e] = mkc<T>((T)(xr - (double)hr), (T)(xi - (double)him));
+    if (lo) lo_st(lo + (long)b * s_s, e, mkc<T>((T)(xr - (double)hr), (T)(xi - (double)him)));
   }
 }
 
