@@ -1120,7 +1120,12 @@ __global__ __launch_bounds__(256) void cost_kernel(const double* __restrict__ si
 // reduce_partials_kernel sums in a fixed order.  Products are formed in T;
 // each lane sums at most ceil(d / 64) * nH of them in T before adding to a
 // float64 accumulator.
-constexpr int NCH = 16;  // row chunks (blocks) per problem of a contraction
+// NCH row chunks (blocks) per problem of a contraction.  64, measured at
+// d = 240, B = 128: the float64 contraction holds 7 blocks per CU, so with
+// 16 chunks its 2048 blocks ran in one full and one small round (79 us per
+// slice); with 64 chunks the rounds are many and short (55 us).  Float32
+// (8 blocks per CU) is the same from 16 to 64.
+constexpr int NCH = 64;
 
 template <typename T>
 struct PairArgs {
