@@ -350,6 +350,13 @@ struct Engine : EngineBase {
   // direction, [slice - cc0[dr]][problem][diagonal][i]; a sweep refills the
   // chunk in the order it walks the slices (coef_hint)
   static constexpr int kCoefChunk = 64;
+  // Stage launches of fewer blocks than this take the serving launch shape
+  // (one or two rows per thread): their blocks finish sooner, which is what
+  // a grid that does not fill the chip waits on.  Measured at d = 240: in
+  // float32 the small shape is 1.4-1.5x faster at 36 and 144 blocks and 3 %
+  // slower at 576; in float64 1.3x faster at 36 and 144, 10 % at 576, even
+  // at 1152.
+  static constexpr long kSmallStageGrid = sizeof(T) == 4 ? 384 : 1024;
   og::cpx<T>* acoef[2];
   int cc0[2] = {0, 0}, cc1[2] = {0, 0};  // slices [cc0, cc1) held; empty when cc1 <= cc0
   struct CoefHint {
@@ -584,8 +591,12 @@ struct Engine : EngineBase {
   // the library maxima.
   template <int MODE, int NA, int ND, bool LAD = false>
   void launch_band_v(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {
-    og::band_stage_kernel<T, MODE, NA, ND, LAD><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(
-        ops, io, ntile, d, coef);
+    if ((long)B * ntile < kSmallStageGrid)
+      og::band_stage_kernel<T, MODE, NA, ND, LAD, og::SlotCfg<T>::NQ><<<stage_grid(), og::slot_threads<T>(), 0, st>>>(
+          ops, io, ntile, d, coef);
+    else
+      og::band_stage_kernel<T, MODE, NA, ND, LAD><<<stage_grid(), og::stage_threads<T>(), 0, st>>>(
+          ops, io, ntile, d, coef);
   }
   template <int MODE>
   void launch_band(const og::BandOps<T>& ops, const og::StageIO<T>& io, const og::cpx<T>* coef) {

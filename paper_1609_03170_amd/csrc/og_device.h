@@ -614,14 +614,16 @@ constexpr int slot_threads() {
 }
 
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
-template <typename T, int MODE, int NA, int ND, bool LAD = false>
-__global__ __launch_bounds__(TS * TS / StageCfg<T>::NQ) void band_stage_kernel(
+// NQ rows per thread: StageCfg for full grids; a small grid takes the
+// serving shape (SlotCfg), whose blocks finish sooner.
+template <typename T, int MODE, int NA, int ND, bool LAD = false, int NQ = StageCfg<T>::NQ>
+__global__ __launch_bounds__(TS * TS / NQ) void band_stage_kernel(
     BandOps<T> ops, StageIO<T> io, int ntile, int d, const cpx<T>* __restrict__ coef) {
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / ntile, t = L - b * ntile;
   if (io.active && !io.active[b]) return;
   const int2 tt = upper_tile(t, d);
-  band_stage_body<T, MODE, NA, ND, StageCfg<T>::NQ, LAD>(
+  band_stage_body<T, MODE, NA, ND, NQ, LAD>(
       ops, resolve_strided(io, b), coef + (long)b * ops.nA * d, io.coef, io.nex, io.status, tt.x * TS, tt.y * TS, d);
 }
 
