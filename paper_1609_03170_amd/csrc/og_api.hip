@@ -359,9 +359,9 @@ struct Engine : EngineBase {
   static constexpr long kSmallStageGrid = sizeof(T) == 4 ? 384 : 1024;
   // Float32 launches of fewer blocks than this (and at least
   // kSmallStageGrid) run two rows per thread, 512 threads: measured at
-  // d = 240, 9 % faster than four rows at 576 blocks, 5 % at 1152, 4 %
-  // slower at 4608.
-  static constexpr long kMidStageGrid = 2048;
+  // d = 240, 9 % faster than four rows at 576 blocks, 5 % at 1152, 3 % at
+  // 2304; 3 % slower at 3456 and 4 % at 4608.
+  static constexpr long kMidStageGrid = 2880;
   og::cpx<T>* acoef[2];
   int cc0[2] = {0, 0}, cc1[2] = {0, 0};  // slices [cc0, cc1) held; empty when cc1 <= cc0
   struct CoefHint {

@@ -14,9 +14,9 @@ from _gpu_util import TOL, gpu_eval, oracle_eval, phi_err, relerr, say
 
 pytestmark = pytest.mark.gpu
 
-# (precision, batch): 6, 600 and 2400 blocks in float32; 6 and 1200 in
+# (precision, batch): 6, 600 and 3000 blocks in float32; 6 and 1200 in
 # float64
-SHAPES = [("f32", 2), ("f32", 200), ("f32", 800), ("f64", 2), ("f64", 400)]
+SHAPES = [("f32", 2), ("f32", 200), ("f32", 1000), ("f64", 2), ("f64", 400)]
 
 
 @pytest.mark.parametrize("prec,B", SHAPES)
