@@ -614,8 +614,9 @@ constexpr int slot_threads() {
 }
 
 // Batched launch: problem b at base + b * stride.  grid.x = B * ntile.
-// NQ rows per thread: StageCfg for full grids; a small grid takes the
-// serving shape (SlotCfg), whose blocks finish sooner.
+// NQ rows per thread, chosen by the host from the number of blocks: StageCfg
+// for full grids, fewer rows per thread (more threads per tile, so that a
+// block finishes sooner) for grids that do not fill the chip.
 template <typename T, int MODE, int NA, int ND, bool LAD = false, int NQ = StageCfg<T>::NQ>
 __global__ __launch_bounds__(TS * TS / NQ) void band_stage_kernel(
     BandOps<T> ops, StageIO<T> io, int ntile, int d, const cpx<T>* __restrict__ coef) {
