@@ -184,6 +184,27 @@ og_status og_set_adaptive(og_ctx *ctx, double rtol, double atol);
 og_status og_set_resident(og_ctx *ctx, int n_slices);
 
 /*
+ * Fused Runge-Kutta steps (the Runge-Kutta integration of Sec. III,
+ * Eq. (14), evaluated four stages per launch).  When the banded operators
+ * have the structure of a multi-level system coupled to an oscillator
+ * (Sec. IV): d = nq N, index q N + n, diagonals of the generator at offsets
+ * 0, +-1 (no coupling between blocks of N) and +-N, dissipator taps
+ * (0, 0), (+-1, +-1) and (+-N, +-N), with nq (T + 6) <= 64 for some tile
+ * edge T >= 2 -- every fixed RK4 step of the forward sweep, its recompute
+ * and the first-order adjoint sweep runs as one kernel that keeps a tile of
+ * the state with a halo of four in on-chip memory through the four nested
+ * stages, instead of four stage kernels that each read and write the whole
+ * state.  The results agree to rounding (the stage inputs are not made
+ * Hermitian in between).  enable = 1 (the default) uses it where the
+ * structure allows; 0 always runs the four stage kernels.  OG_ERR_ORDER
+ * while a server has requests in flight; invalidates a preceding og_forward.
+ * og_fused_used returns 1 when the context's fixed steps run fused (both
+ * directions), else 0.
+ */
+og_status og_set_fused(og_ctx *ctx, int enable);
+int og_fused_used(const og_ctx *ctx);
+
+/*
  * Step counts of the last evaluation, per problem: counts (host, long
  * B x 4) = [accepted forward, rejected forward, accepted adjoint, rejected
  * adjoint] (the checkpoint recompute repeats the forward steps and is not
@@ -225,6 +246,17 @@ size_t og_workspace_bytes(const og_ctx *ctx, int B, int n_t);
 og_status og_forward(og_ctx *ctx, int B, int n_t, double dt,
                      const double *u, const void *rho0, void *rhoT,
                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Number of successful og_forward calls on ctx so far (0 before the first).
+ * og_cost, og_adjoint and og_gradient always work on the last forward sweep;
+ * a caller that keeps several evaluations in flight on one context (an
+ * autograd graph holding two applications of the same cost) records this
+ * value after its og_forward and compares it before og_adjoint: a different
+ * value means another forward sweep has replaced its own in the workspace,
+ * which must then be run again.
+ */
+unsigned long long og_generation(const og_ctx *ctx);
 
 /*
  * Performance index (Eq. (8)): phi[b] = Re Tr(sigma rho_{N_t}[b]), summed
@@ -274,7 +306,9 @@ og_status og_gradient_sum(og_ctx *ctx, double *grad, int accumulate, void *strea
  * backward sweep give the gradient of the penalised index (both gradient
  * modes).  A: host complex128 d x d, Hermitian (validate = 1 checks it).
  * beta = 0 or A = NULL removes the penalty.  Synchronous; set it before
- * og_forward.  Not supported by the server.
+ * og_forward: the call invalidates a preceding og_forward (og_cost,
+ * og_adjoint, og_gradient then return OG_ERR_ORDER until the next
+ * og_forward).  Not supported by the server.
  */
 og_status og_set_penalty(og_ctx *ctx, const void *A, double beta);
 

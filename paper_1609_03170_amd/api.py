@@ -40,7 +40,7 @@ EXPORTS = (
     "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
     "og_server_destroy", "og_status_string", "og_last_error", "og_gradient_sum", "og_set_penalty",
     "og_filter_apply", "og_filter_grad", "og_create_banded", "og_set_adaptive", "og_adaptive_stats",
-    "og_set_resident",
+    "og_set_resident", "og_generation", "og_set_fused", "og_fused_used",
 )
 
 
@@ -108,6 +108,12 @@ def load_library(path: str = LIB_PATH):
     lib.og_adaptive_stats.restype = i
     lib.og_set_resident.argtypes = [vp, i]
     lib.og_set_resident.restype = i
+    lib.og_set_fused.argtypes = [vp, i]
+    lib.og_set_fused.restype = i
+    lib.og_fused_used.argtypes = [vp]
+    lib.og_fused_used.restype = i
+    lib.og_generation.argtypes = [vp]
+    lib.og_generation.restype = ctypes.c_ulonglong
     lib.og_filter_apply.argtypes = [i, i, i, i, d, d, d, vp, vp, vp]
     lib.og_filter_apply.restype = i
     lib.og_filter_grad.argtypes = [i, i, i, i, d, d, d, i, vp, vp, vp]
@@ -244,6 +250,7 @@ class Problem:
         if getattr(self, "_ctx", None):
             self._lib.og_destroy(self._ctx)
             self._ctx = None
+        self._keep = {}  # the workspace and inputs of the last evaluation
 
     def __del__(self):
         try:
@@ -286,6 +293,11 @@ class Problem:
                                         rhoT.data_ptr() if rhoT is not None else None,
                                         workspace.data_ptr(), need, _stream_ptr(self.device)))
         return rhoT
+
+    @property
+    def generation(self) -> int:
+        """Number of forward sweeps run on this Problem (og_generation)."""
+        return int(self._lib.og_generation(self._ctx))
 
     def cost(self, sigma):
         sigma = self._as_states(sigma, 1)[0].contiguous()
@@ -350,6 +362,16 @@ class Problem:
         with torch.cuda.device(self.device):
             _check(self._lib.og_set_resident(self._ctx, int(n_slices)))
 
+    def set_fused(self, enable: bool):
+        """Fused RK4 steps (four stages per launch) where the operator
+        structure allows (default on), or always the four stage kernels."""
+        _check(self._lib.og_set_fused(self._ctx, int(bool(enable))))
+
+    @property
+    def fused(self) -> bool:
+        """True when the fixed RK4 steps of this Problem run fused."""
+        return bool(self._lib.og_fused_used(self._ctx))
+
     def resident_for_budget(self, B, n_t, budget_bytes):
         """Largest number of resident slices (up to n_t) whose workspace
         fits in budget_bytes, 0 when none fits; leaves the setting at 0."""
@@ -413,21 +435,31 @@ class OpenGrapeCost(torch.autograd.Function):
 
     forward: og_forward + og_cost; backward: og_adjoint + og_gradient, which
     must run in the exact mode (the first-order Eq. (13) gradient is not the
-    derivative of the computed Phi)."""
+    derivative of the computed Phi).  The workspace of a Problem holds the
+    states of its last forward sweep only: when another application of the
+    same Problem ran a forward sweep in between (og_generation changed),
+    backward runs this application's forward sweep again before the adjoint,
+    so every application gets its own gradient."""
 
     @staticmethod
     def forward(ctx, u, problem, rho0, sigma, dt):
         if problem.gmode != "exact":
             raise ValueError("OpenGrapeCost needs a Problem created with gmode='exact'")
-        problem.forward(u.detach(), rho0, dt)
+        u_in = u.detach()
+        problem.forward(u_in, rho0, dt)
         phi = problem.cost(sigma)
         ctx.problem = problem
         ctx.sigma = sigma
+        ctx.inputs = (u_in, rho0, dt)
+        ctx.generation = problem.generation
         ctx.squeeze = u.dim() == 2
         return phi[0] if ctx.squeeze else phi
 
     @staticmethod
     def backward(ctx, gphi):
+        if ctx.problem.generation != ctx.generation:
+            u_in, rho0, dt = ctx.inputs
+            ctx.problem.forward(u_in, rho0, dt)
         ctx.problem.adjoint(ctx.sigma)
         g = ctx.problem.gradient()
         if ctx.squeeze:

@@ -241,6 +241,7 @@ struct EngineBase {
   virtual og_status gradient(double* grad, hipStream_t st) = 0;
   virtual og_status gradient_sum(double* grad, int accumulate, hipStream_t st) = 0;
   virtual og_status adaptive_stats(long* counts) = 0;
+  virtual int fused_used() const = 0;
   // continuous batching (og_server_*)
   virtual og_status serve_submit(const og_request& r, hipStream_t st) = 0;
   virtual og_status serve_step(int max_slices, hipStream_t st, std::vector<long>& done) = 0;
@@ -259,6 +260,7 @@ struct og_ctx {
   og_options opt{};
   int path = OG_PATH_DENSE;
   int phase = 0;  // 0: nothing, 1: forward done, 2: adjoint done
+  unsigned long long generation = 0;  // successful og_forward calls
   EngineBase* eng = nullptr;
   // host data for the stability estimate
   std::vector<double> h0_diag, h0_rad, hk_gersh, hk_frob;
@@ -274,6 +276,7 @@ struct og_ctx {
   // og_set_resident: final slices of the forward sweep whose states stay in
   // device memory (no checkpoint recompute for them)
   int resident = 0;
+  int fused_on = 1;          // og_set_fused: fused RK4 steps where the structure allows
   int* host_flag = nullptr;  // pinned: problems still active after an attempt
   // kernel timing samples (og_profile)
   int prof_every = 0;
@@ -330,6 +333,12 @@ struct Engine : EngineBase {
   DirDev<T> dir[2];
   og::HBand<T> hband{};
   og::cpx<T>* hHd = nullptr;   // banded H_k diagonals
+  // fused RK4 step (rk4_fused_kernel) per direction, when the operators have
+  // the multi-level x oscillator structure it needs
+  bool fused[2] = {false, false};
+  og::FusedGeo fgeo[2]{};
+  size_t fused_lds[2] = {0, 0};
+  static constexpr int kFusedNW = sizeof(T) == 4 ? 4 : 8;  // waves per block
   og::cpx<T>* HT = nullptr;    // dense: transposes of H_k, K x d x d
   int ntile = 0;
   static constexpr bool comp = sizeof(T) == 4;  // compensated states in float32
@@ -340,6 +349,7 @@ struct Engine : EngineBase {
   const double* u = nullptr;
   // workspace views
   og::cpx<T>*cur_hi, *cur_lo, *lam_hi, *lam_lo, *Za, *Zb;
+  og::cpx<T>* cur_base = nullptr;  // the buffer cur_hi is bound to (the fused step swaps buffers)
   og::cpx<T>*ck_hi, *ck_lo, *sg_hi, *sg_lo;
   og::cpx<T>* tail = nullptr;  // resident states rho_{n_t - n_tail} .. rho_{n_t}
   int n_tail = 0;
@@ -407,6 +417,82 @@ struct Engine : EngineBase {
     if (HT) (void)hipFree(HT);
   }
 
+  // Structure test of the fused RK4 step (rk4_fused_kernel) for direction
+  // s, on the ladder-ordered diagonals offs (values a0, ak[k]) and dissipator
+  // taps (tp, tq, values dl, dr): offsets 0, +-1 and +-N with d = nq N, taps
+  // (0, 0), (s, s) with s = +-1 and (t, t) with t = +-N; the +-1 couplings
+  // must vanish between blocks of N (rows n = N - 1 for +1, n = 0 for -1),
+  // and the tile edge T must fit the lane mapping (nq (T + 6) <= 64) and
+  // the LDS (at most 64 KiB).  Otherwise the four-launch stage kernels run.
+  void fused_setup(int s, const std::vector<int>& offs, const std::vector<int>& tp, const std::vector<int>& tq,
+                   const std::vector<cd>& a0, const std::vector<std::vector<cd>>& ak,
+                   const std::vector<std::vector<cd>>& dl, const std::vector<std::vector<cd>>& dr) {
+    fused[s] = false;
+    const og::BandOps<T>& ops = dir[s].band;
+    const int nA = (int)offs.size(), nD = (int)tp.size();
+    if (!ops.lad || nA > og::FMAXA || nD > og::FMAXD || nA < 3 || nD < 2) return;
+    if (offs[0] != 0 || offs[1] != 1 || offs[2] != -1 || tp[0] != 0 || tq[0] != 0) return;
+    if (tp[1] != tq[1] || (tp[1] != 1 && tp[1] != -1)) return;
+    int N = 0;  // block length from the offsets beyond 0, +-1 and the taps beyond (0,0), (s,s)
+    auto take = [&](int o) {
+      const int a = o < 0 ? -o : o;
+      if (N == 0) N = a;
+      return a == N;
+    };
+    for (int a = 3; a < nA; ++a)
+      if (!take(offs[a])) return;
+    for (int t = 2; t < nD; ++t)
+      if (tp[t] != tq[t] || !take(tp[t])) return;
+    if (N == 0) N = d;
+    if (N < 2 || d % N != 0) return;
+    const int nq = d / N;
+    // no +-1 coupling across a block boundary (A(u) for every u, and the (s,s) tap)
+    for (int i = 0; i < d; ++i) {
+      const int n = i % N;
+      if (n == N - 1) {
+        if (a0[(size_t)1 * d + i] != cd(0, 0)) return;
+        for (auto& v : ak)
+          if (v[(size_t)1 * d + i] != cd(0, 0)) return;
+      }
+      if (n == 0) {
+        if (a0[(size_t)2 * d + i] != cd(0, 0)) return;
+        for (auto& v : ak)
+          if (v[(size_t)2 * d + i] != cd(0, 0)) return;
+      }
+      if ((tp[1] > 0 && n == N - 1) || (tp[1] < 0 && n == 0))
+        if (dl[1][i] != cd(0, 0) || dr[1][i] != cd(0, 0)) return;
+    }
+    // tile edge: the widest that fits the lanes and the LDS
+    const int tlane = 64 / nq - 6;
+    if (tlane < 2) return;
+    for (int nb = (N + tlane - 1) / tlane; nb <= N; ++nb) {
+      const int tmax = (N + nb - 1) / nb;
+      const int wmax = std::min(tmax + 8, N);
+      const size_t bytes = (size_t)og::fused_lds_elems(nq, wmax, tmax) * sizeof(og::cpx<T>);
+      if (bytes > 65536) continue;
+      og::FusedGeo& g = fgeo[s];
+      g = og::FusedGeo{};
+      g.N = N;
+      g.nq = nq;
+      g.nb = nb;
+      g.ntile = nb * (nb + 1) / 2;
+      g.nA = nA;
+      g.nD = nD;
+      auto split = [&](int o, int& q, int& n) {
+        q = (o == N) ? 1 : (o == -N ? -1 : 0);
+        n = q != 0 ? 0 : o;
+      };
+      for (int a = 0; a < nA; ++a) split(offs[a], g.aq[a], g.an[a]);
+      for (int t = 0; t < nD; ++t) split(tp[t], g.tq[t], g.tn[t]);
+      if (nq == 1) {  // N = d: no q couplings; offsets +-1 are n steps
+        for (int a = 0; a < nA; ++a) g.aq[a] = 0, g.an[a] = offs[a];
+      }
+      fused_lds[s] = bytes;
+      fused[s] = true;
+      return;
+    }
+  }
+
   og_status init(const DirHost host[2], const std::vector<Mat>& Hk) {
     // upper-triangular tiles (the kernels compute a tile's position from its index)
     const int nt = (d + og::TS - 1) / og::TS;
@@ -455,6 +541,7 @@ struct Engine : EngineBase {
         dv.band.Ak = dv.bAk;
         dv.band.Dl = dv.bDl;
         dv.band.Dr = dv.bDr;
+        fused_setup(s, offs, tp, tq, dia_values(h.A0, offs), ak, dl, dr);
       } else {
         OG_TRY(upload<T>(h.A0.a, &dv.A0));
         std::vector<std::vector<cd>> ak, cc, ch;
@@ -759,12 +846,65 @@ struct Engine : EngineBase {
     return OG_OK;
   }
 
-  // n_sub RK4 steps of slice j in direction dr: (in) -> (out); in == out allowed.
+  bool use_fused(int dr) const { return banded && fused[dr] && ctx->fused_on; }
+  int fused_used() const override { return use_fused(FWD) && use_fused(ADJ) ? 1 : 0; }
+
+  // One fused RK4 step (the four nested stages in one launch) for the whole
+  // batch: (ihi, ilo) -> (ohi, olo).  ohi must differ from ihi (other tiles
+  // read the halo of the input while the output is written); olo may equal
+  // ilo (every element's compensation term is read and written by one block).
+  og_status fused_step(int dr, int jslice, const og::cpx<T>* ihi, const og::cpx<T>* ilo, og::cpx<T>* ohi,
+                       og::cpx<T>* olo, T h) {
+    og::StageIO<T> io = io_base();
+    io.in = ihi;
+    io.shi = ihi;
+    io.slo = ilo;
+    io.ohi = ohi;
+    io.olo = olo;
+    const long pidx = ctx->prof_begin(st);
+    og::rk4_fused_kernel<T, kFusedNW><<<dim3((unsigned)(B * fgeo[dr].ntile)), kFusedNW * 64, fused_lds[dr], st>>>(
+        dir[dr].band, fgeo[dr], io, d, coef_ptr(dr, jslice), h);
+    OG_CHECK_LAUNCH();
+    ctx->prof_end(pidx, st);
+    return OG_OK;
+  }
+
+  // n_sub RK4 steps of slice j in direction dr on the state (hi, lo) "in
+  // place": with the fused step every step writes the other buffer of the
+  // pair (hi, alt) and the two pointers are swapped, so hi holds the result.
+  og_status advance(int dr, int jslice, og::cpx<T>*& hi, og::cpx<T>* lo, og::cpx<T>*& alt) {
+    if (!use_fused(dr)) return rk_slice(dr, jslice, hi, lo, hi, lo);
+    const int nsub = ctx->opt.n_sub;
+    const T h = (T)(dt / nsub);
+    OG_TRY(assemble(dr, jslice));
+    for (int s = 0; s < nsub; ++s) {
+      OG_TRY(fused_step(dr, jslice, hi, lo, alt, lo, h));
+      std::swap(hi, alt);
+    }
+    return OG_OK;
+  }
+
+  // n_sub RK4 steps of slice j in direction dr: (in) -> (out).  in == out is
+  // allowed for the four-launch stages only (callers use advance() for
+  // in-place steps); with the fused step several substeps alternate between
+  // out and Zb so that the last one writes out.
   og_status rk_slice(int dr, int jslice, const og::cpx<T>* ihi, const og::cpx<T>* ilo, og::cpx<T>* ohi,
                      og::cpx<T>* olo) {
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dt / nsub);
     OG_TRY(assemble(dr, jslice));
+    if (use_fused(dr)) {
+      if (ihi == ohi) return fail(OG_ERR_ARG, "internal: fused RK4 step in place");
+      const og::cpx<T>* src = ihi;
+      const og::cpx<T>* slo = ilo;
+      for (int s = 0; s < nsub; ++s) {
+        og::cpx<T>* dst = ((nsub - 1 - s) % 2 == 0) ? ohi : Zb;
+        OG_TRY(fused_step(dr, jslice, src, slo, dst, olo, h));
+        src = dst;
+        slo = olo;
+      }
+      return OG_OK;
+    }
     for (int s = 0; s < nsub; ++s) {
       const og::cpx<T>* shi = s == 0 ? ihi : ohi;
       const og::cpx<T>* slo = s == 0 ? ilo : olo;
@@ -943,7 +1083,7 @@ struct Engine : EngineBase {
     auto at = [&](int i) { return reinterpret_cast<og::cpx<T>*>(p + L.off[i]); };
     auto opt_at = [&](int i, bool use) { return use ? at(i) : nullptr; };
     const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
-    cur_hi = at(L_CUR_HI);
+    cur_hi = cur_base = at(L_CUR_HI);
     cur_lo = opt_at(L_CUR_LO, comp);
     lam_hi = at(L_LAM_HI);
     lam_lo = opt_at(L_LAM_LO, comp);
@@ -1037,8 +1177,13 @@ struct Engine : EngineBase {
       if (ad)
         OG_TRY(adaptive_slice(FWD, j, cur_hi, cur_lo, dpc[DP_FWD]));
       else
-        OG_TRY(rk_slice(FWD, j, cur_hi, cur_lo, cur_hi, cur_lo));
+        OG_TRY(advance(FWD, j, cur_hi, cur_lo, Za));
       OG_TRY(penalty_trace(j + 1));
+    }
+    if (cur_hi != cur_base) {  // the fused step left the state in the other buffer
+      OG_TRY(copy_hi(cur_base, cur_hi));
+      Za = cur_hi;
+      cur_hi = cur_base;
     }
     if (n_tail > 0) {
       // the tail runs on the stored states; the compensation term stays in
@@ -1143,7 +1288,7 @@ struct Engine : EngineBase {
       if (ad)
         OG_TRY(adaptive_slice(ADJ, j, lam_hi, lam_lo, dpc[DP_ADJ]));
       else
-        OG_TRY(rk_slice(ADJ, j, lam_hi, lam_lo, lam_hi, lam_lo));
+        OG_TRY(advance(ADJ, j, lam_hi, lam_lo, Za));
       return penalty_inject();
     }
     // exact derivative of the RK4-discretised Phi: reverse through the
@@ -1303,10 +1448,82 @@ struct Engine : EngineBase {
   }
 
   // One slice operation (n_sub RK4 steps) for up to MAXSLOT requests of the
-  // same direction and slice length; adjoint operations first contract the
-  // first-order gradient of their slice.
+  // same direction and slice length (MAXFSLOT with the fused step); adjoint
+  // operations first contract the first-order gradient of their slice.
   og_status run_chunk(int dr, const std::vector<Op>& ops, size_t i0, size_t i1, double dtv) {
     const int n = (int)(i1 - i0);
+    // contraction and coefficients: sub-launches of at most MAXSLOT requests
+    for (int q0 = 0; q0 < n; q0 += og::MAXSLOT) {
+      const int m = std::min(og::MAXSLOT, n - q0);
+      if (dr == ADJ && K > 0) {
+        og::PairSlots<T> ps{};
+        for (int q = 0; q < m; ++q) {
+          const Op& o = ops[i0 + q0 + q];
+          const Slot& sl = slots[o.slot];
+          ps.X[q] = o.pairX;
+          ps.L[q] = sl.lam_hi;
+          ps.out[q] = sl.part + (long)o.slice * og::NCH * K;
+        }
+        const dim3 cg((unsigned)(og::NCH * m));
+        if (hband.nH <= 4)
+          og::band_contract_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
+        else if (hband.nH <= 8)
+          og::band_contract_slots_kernel<T, 8><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
+        else
+          og::band_contract_slots_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
+        OG_CHECK_LAUNCH();
+      }
+      og::SlotTable<T> ct{};
+      for (int q = 0; q < m; ++q) {
+        const Op& o = ops[i0 + q0 + q];
+        const Slot& sl = slots[o.slot];
+        ct.e[q].coef = dr == FWD ? sl.coefF : sl.coefA;
+        ct.e[q].urow = sl.r.u + (long)o.slice * K;
+      }
+      const int na = dir[dr].band.nA * d;
+      const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
+      og::band_coef_slots_kernel<T><<<dim3(gx, (unsigned)m), 256, 0, st>>>(dir[dr].band, ct, d, K);
+      OG_CHECK_LAUNCH();
+    }
+    const int nsub = ctx->opt.n_sub;
+    const T h = (T)(dtv / nsub);
+    if (use_fused(dr)) {
+      // In-place operations (the forward state, lambda) write the request's
+      // other buffer (za for the state, zb for lambda) and swap the two;
+      // the segment recompute (sg[jj] -> sg[jj + 1]) chains several substeps
+      // through za so that the last one writes sg[jj + 1].
+      std::vector<const og::cpx<T>*> prev((size_t)n);
+      for (int sub = 0; sub < nsub; ++sub) {
+        og::FusedSlotTable<T> ft{};
+        for (int q = 0; q < n; ++q) {
+          const Op& o = ops[i0 + q];
+          Slot& sl = slots[o.slot];
+          og::FusedSlot<T>& e = ft.e[q];
+          e.coef = dr == FWD ? sl.coefF : sl.coefA;
+          if (o.ihi == o.ohi) {
+            og::cpx<T>*& cur = dr == FWD ? sl.cur_hi : sl.lam_hi;
+            og::cpx<T>*& alt = dr == FWD ? sl.za : sl.zb;
+            e.s_hi = cur;
+            e.o_hi = alt;
+            e.s_lo = e.o_lo = dr == FWD ? sl.cur_lo : sl.lam_lo;
+            std::swap(cur, alt);
+          } else {
+            e.s_hi = sub == 0 ? o.ihi : prev[q];
+            e.s_lo = sub == 0 ? o.ilo : o.olo;
+            e.o_hi = ((nsub - 1 - sub) % 2 == 0) ? o.ohi : sl.za;
+            e.o_lo = o.olo;
+            prev[q] = e.o_hi;
+          }
+        }
+        const long pidx = ctx->prof_begin(st);
+        og::rk4_fused_slots_kernel<T, kFusedNW><<<dim3((unsigned)(n * fgeo[dr].ntile)), kFusedNW * 64,
+                                                 fused_lds[dr], st>>>(dir[dr].band, fgeo[dr], ft, h,
+                                                                      ctx->status_dev, d);
+        OG_CHECK_LAUNCH();
+        ctx->prof_end(pidx, st);
+      }
+      return OG_OK;
+    }
     og::SlotTable<T> tab{};
     for (int q = 0; q < n; ++q) {
       const Op& o = ops[i0 + q];
@@ -1321,30 +1538,6 @@ struct Engine : EngineBase {
       e.coef = dr == FWD ? sl.coefF : sl.coefA;
       e.urow = sl.r.u + (long)o.slice * K;
     }
-    if (dr == ADJ && K > 0) {
-      og::PairSlots<T> ps{};
-      for (int q = 0; q < n; ++q) {
-        const Op& o = ops[i0 + q];
-        const Slot& sl = slots[o.slot];
-        ps.X[q] = o.pairX;
-        ps.L[q] = sl.lam_hi;
-        ps.out[q] = sl.part + (long)o.slice * og::NCH * K;
-      }
-      const dim3 cg((unsigned)(og::NCH * n));
-      if (hband.nH <= 4)
-        og::band_contract_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
-      else if (hband.nH <= 8)
-        og::band_contract_slots_kernel<T, 8><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
-      else
-        og::band_contract_slots_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
-      OG_CHECK_LAUNCH();
-    }
-    const int na = dir[dr].band.nA * d;
-    const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
-    og::band_coef_slots_kernel<T><<<dim3(gx, (unsigned)n), 256, 0, st>>>(dir[dr].band, tab, d, K);
-    OG_CHECK_LAUNCH();
-    const int nsub = ctx->opt.n_sub;
-    const T h = (T)(dtv / nsub);
     for (int sub = 0; sub < nsub; ++sub) {
       if (sub == 1)
         for (int q = 0; q < n; ++q) {
@@ -1361,13 +1554,15 @@ struct Engine : EngineBase {
 
   og_status run_group(int dr, std::vector<Op>& ops) {
     // same slice length in one launch: sort by dt, then chunks of MAXSLOT
+    // (MAXFSLOT with the fused step)
     std::stable_sort(ops.begin(), ops.end(),
                      [&](const Op& a, const Op& b) { return slots[a.slot].r.dt < slots[b.slot].r.dt; });
+    const size_t cap = use_fused(dr) ? (size_t)og::MAXFSLOT : (size_t)og::MAXSLOT;
     size_t i = 0;
     while (i < ops.size()) {
       const double dtv = slots[ops[i].slot].r.dt;
       size_t k = i;
-      while (k < ops.size() && k - i < (size_t)og::MAXSLOT && slots[ops[k].slot].r.dt == dtv) ++k;
+      while (k < ops.size() && k - i < cap && slots[ops[k].slot].r.dt == dtv) ++k;
       OG_TRY(run_chunk(dr, ops, i, k, dtv));
       i = k;
     }
@@ -1719,6 +1914,17 @@ og_status og_set_resident(og_ctx* ctx, int n_slices) {
   return OG_OK;
 }
 
+og_status og_set_fused(og_ctx* ctx, int enable) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (ctx->eng->serve_active() > 0) return fail(OG_ERR_ORDER, "requests are in flight on this context");
+  ctx->fused_on = enable ? 1 : 0;
+  ctx->phase = 0;
+  return OG_OK;
+}
+
+int og_fused_used(const og_ctx* ctx) { return ctx && ctx->eng ? ctx->eng->fused_used() : 0; }
+
 og_status og_adaptive_stats(og_ctx* ctx, long* counts) {
   g_err.clear();
   if (!ctx || !ctx->eng || !counts) return fail(OG_ERR_ARG, "ctx or counts is NULL");
@@ -1791,8 +1997,11 @@ og_status og_forward(og_ctx* ctx, int B, int n_t, double dt, const double* u, co
   if (ctx->opt.validate) OG_TRY(check_stability(ctx, u, (long)B * n_t, dt, st));
   OG_TRY(ctx->eng->forward(B, n_t, dt, u, rho0, rhoT, ws, ws_bytes, st));
   ctx->phase = 1;
+  ++ctx->generation;
   return OG_OK;
 }
+
+unsigned long long og_generation(const og_ctx* ctx) { return ctx ? ctx->generation : 0; }
 
 og_status og_cost(og_ctx* ctx, const void* sigma, double* phi, void* stream) {
   g_err.clear();
@@ -1854,6 +2063,9 @@ og_status og_set_penalty(og_ctx* ctx, const void* A, double beta) {
     ctx->pen_nnz = 0;
   }
   ctx->pen_beta = 0.0;
+  // the index changes: a forward sweep recorded without (or with another)
+  // penalty no longer matches, so cost / adjoint wait for the next og_forward
+  ctx->phase = 0;
   if (beta == 0.0 || !A) return OG_OK;
   const int d = ctx->d;
   Mat a = from_ptr(A, d, 0);

@@ -684,6 +684,328 @@ __global__ __launch_bounds__(TS * TS / SlotCfg<T>::NQ) void band_stage_slots_ker
 }
 
 // ---------------------------------------------------------------------------
+// Fused Runge-Kutta step: the four nested stages of one RK4 step (Horner
+// form Z1 = rho + h/4 L(rho), Z2 = rho + h/3 L(Z1), Z3 = rho + h/2 L(Z2),
+// rho' = rho + h L(Z3)) in one launch, for operators with the structure of
+// a multi-level system of nq levels coupled to an oscillator of N levels
+// (the transmon x resonator models of Sec. IV): d = nq N, index i = q N + n;
+// A(u) has diagonals at offsets 0, +-1 (never linking one block of N to the
+// next) and +-N; the dissipator taps are (0, 0), (s, s) with s = +-1, and
+// (t, t) with t = +-N.  One stage of L then reaches one step in n and one
+// step in q.  A block computes the step on one tile of n-ranges
+// [r0, r1) x [c0, c1) for all nq x nq level pairs, so the q-couplings stay
+// inside the tile and the n-halo grows by one per stage: the tile and a halo
+// of 4 in n are read from global memory into LDS once, the stages run on
+// shrinking regions of it (halo 3, 2, 1, then the tile itself), and only
+// the new state is written back: one read and one write of the state per
+// RK4 step instead of four of each.
+//
+// Only the tiles with row block <= column block are computed; the new state
+// is written at (i, j) and, conjugated, at (j, i), so it stays exactly
+// Hermitian (on a diagonal tile the pair with n_r < n_c, or n_r = n_c and
+// q_r <= q_c, is the one computed and written; its diagonal elements get a
+// zero imaginary part).  The intermediate stages need not be Hermitian and
+// are not made so.
+//
+// Work mapping: lane l of every wave owns one column (q_c, n_c) of the
+// stage-0 region (nq (T + 6) <= 64 columns, T the tile edge); wave w owns
+// the rows w, w + NW, ... of the stage-0 region, so the row index and the
+// row coefficients of A(u) and of the dissipators are wave-uniform (scalar
+// loads) and the column coefficients stay in registers.  The state rho of a
+// thread's elements stays in registers across the stages; a stage's outputs
+// are held in registers until every wave has read the stage input, then
+// written over it (one LDS buffer).  Taps that would leave the window or the
+// matrix have zero coefficients (checked on the host); their LDS addresses
+// stay inside the buffer (zero-filled pads of one row and one element at
+// both ends) or are redirected to the element itself.
+// ---------------------------------------------------------------------------
+constexpr int FMAXA = 5;  // diagonals: 0, +1, -1, +N, -N
+constexpr int FMAXD = 3;  // dissipator taps: (0, 0), (s, s), (t, t)
+
+struct FusedGeo {
+  int N, nq;                 // d = nq N
+  int nb;                    // n-blocks per axis; block k is [k N / nb, (k + 1) N / nb)
+  int ntile;                 // nb (nb + 1) / 2 tiles per problem
+  int nA, nD;                // diagonals / dissipator taps in use (ladder order)
+  int aq[FMAXA], an[FMAXA];  // diagonal a: offset aq N + an
+  int tq[FMAXD], tn[FMAXD];  // dissipator tap t: (p, p) with p = tq N + tn
+};
+
+// (row block, column block) of upper tile t of an nb x nb grid, row-major.
+__device__ __forceinline__ int2 fused_tile(int t, int nb) {
+  int r = 0;
+  while (t >= nb - r) {
+    t -= nb - r;
+    ++r;
+  }
+  return make_int2(r, r + t);
+}
+
+// LDS elements (cpx<T>) the fused step needs for a window of at most
+// wmax x wmax per level pair: the window with its pads, or the staging of
+// the tile's new state (hi and lo) for the transposed write, if larger.
+__host__ __device__ __forceinline__ int fused_lds_elems(int nq, int wmax, int tmax) {
+  const int win = nq * nq * wmax * wmax + 2 * (nq * wmax + 1);
+  const int stg = 2 * nq * nq * tmax * tmax;
+  return win > stg ? win : stg;
+}
+
+template <typename T, int NW>
+__device__ __forceinline__ void rk4_fused_body(const BandOps<T>& ops, const FusedGeo& g, const ProbPtr<T>& P,
+                                               const cpx<T>* __restrict__ cb, T h, int* status, int t, int d,
+                                               cpx<T>* __restrict__ buf) {
+  constexpr int NR = 64 / NW;  // stage-0 rows per wave: nq (T + 6) <= 64 rows in all
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int N = g.N, nq = g.nq, nb = g.nb, nA = g.nA, nD = g.nD;
+  const int2 tb = fused_tile(t, nb);
+  const bool dtile = tb.x == tb.y;
+  const int r0 = tb.x * N / nb, r1 = (tb.x + 1) * N / nb;
+  const int c0 = tb.y * N / nb, c1 = (tb.y + 1) * N / nb;
+  // window: the tile with a halo of 4 in n, clipped to [0, N)
+  const int wr0 = max(r0 - 4, 0), Wr = min(r1 + 4, N) - wr0;
+  const int wc0 = max(c0 - 4, 0), Wc = min(c1 + 4, N) - wc0;
+  const int RS = nq * Wc;   // LDS stride of one row (q_r, n_r)
+  const int QS = Wr * RS;   // LDS stride of one level q_r
+  const int PAD = RS + 1;
+  const int nwin = nq * QS;
+  // stage-0 output region: halo 3
+  const int rs0 = max(r0 - 3, 0), h0 = min(r1 + 3, N) - rs0;
+  const int cs0 = max(c0 - 3, 0), w0 = min(c1 + 3, N) - cs0;
+  const int nrow0 = nq * h0;
+  const cpx<T>* __restrict__ Y = P.in;
+
+  // ---- window -> LDS (rows by wave, columns by lane; two lane passes) ----
+  {
+    int goff[2], ok[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int c = lane + 64 * p;
+      ok[p] = c < RS;
+      const int qc = ok[p] ? c / Wc : 0;
+      goff[p] = qc * N + wc0 + (c - qc * Wc);
+    }
+    for (int k = wave; k < nq * Wr; k += NW) {
+      const int qr = k / Wr;
+      const unsigned grow = __umul24(qr * N + wr0 + (k - qr * Wr), d);
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+        if (ok[p]) buf[PAD + k * RS + lane + 64 * p] = ldm(Y, grow + goff[p]);
+    }
+    for (int e = tid; e < PAD; e += 64 * NW) {
+      buf[e] = mkc<T>(0, 0);
+      buf[PAD + nwin + e] = mkc<T>(0, 0);
+    }
+  }
+
+  // ---- this lane's column ----
+  const bool act0 = lane < nq * w0;
+  const int qc = act0 ? lane / w0 : 0;
+  const int n_c = cs0 + (lane - qc * w0);
+  const int jcol = qc * N + n_c;
+  const int lcol = qc * Wc + (n_c - wc0);
+  cpx<T> cC[FMAXA], dC[FMAXD];
+#pragma unroll
+  for (int a = 0; a < FMAXA; ++a) cC[a] = (act0 && a < nA) ? cb[a * d + jcol] : mkc<T>(0, 0);
+#pragma unroll
+  for (int s = 0; s < FMAXD; ++s) dC[s] = (act0 && s < nD) ? ops.Dr[s * d + jcol] : mkc<T>(0, 0);
+  int dCa[FMAXA], dCt[FMAXD];
+#pragma unroll
+  for (int a = 0; a < FMAXA; ++a) dCa[a] = a < nA ? g.aq[a] * Wc + g.an[a] : 0;
+#pragma unroll
+  for (int s = 0; s < FMAXD; ++s) dCt[s] = s < nD ? g.tq[s] * Wc + g.tn[s] : 0;
+
+  __syncthreads();
+
+  // ---- this wave's rows (level, n; wave-uniform) and rho of the own elements ----
+  int rq[NR], rn[NR];
+  cpx<T> rho[NR], z[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int k = wave + NW * q;
+    rq[q] = k / h0;
+    rn[q] = k < nrow0 ? rs0 + (k - rq[q] * h0) : -1;  // -1: no row (outside every region)
+    rho[q] = mkc<T>(0, 0);
+    z[q] = mkc<T>(0, 0);
+    if (rn[q] >= 0 && act0) rho[q] = buf[PAD + (rq[q] * Wr + rn[q] - wr0) * RS + lcol];
+  }
+
+  // L(Y) at row (qr, nr) (wave-uniform) and this lane's column, Y in LDS.
+  auto lval = [&](int qr, int nr) -> cpx<T> {
+    const int i = qr * N + nr;
+    const int base = PAD + (qr * Wr + nr - wr0) * RS + lcol;
+    cpx<T> acc = mkc<T>(0, 0);
+    const cpx<T> y0 = buf[base];
+#pragma unroll
+    for (int a = 0; a < FMAXA; ++a)
+      if (a < nA) {
+        const cpx<T> cr = cb[a * d + i];
+        const int qq = qr + g.aq[a];
+        const int dr = (qq >= 0 && qq < nq) ? g.aq[a] * QS + g.an[a] * RS : 0;
+        const cpx<T> yr = a == 0 ? y0 : buf[base + dr];
+        const cpx<T> yc = a == 0 ? y0 : buf[base + dCa[a]];
+        cfma(acc, cr, yr);
+        cfmac(acc, yc, cC[a]);
+      }
+#pragma unroll
+    for (int s = 0; s < FMAXD; ++s)
+      if (s < nD) {
+        const cpx<T> dl = ops.Dl[s * d + i];
+        const int qq = qr + g.tq[s];
+        const int dr = (qq >= 0 && qq < nq) ? g.tq[s] * QS + g.tn[s] * RS : 0;
+        const cpx<T> yd = s == 0 ? y0 : buf[base + dr + dCt[s]];
+        cfma(acc, cmulc(dl, dC[s]), yd);
+      }
+    return acc;
+  };
+
+  // ---- stages 0..2: Z_{s+1} = rho + c_s L(Z_s) on the region of halo 3 - s ----
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const T cs = s == 0 ? h / T(4) : (s == 1 ? h / T(3) : h / T(2));
+    const int hs = 3 - s;
+    const int rlo = max(r0 - hs, 0), rhi = min(r1 + hs, N);
+    const bool lact = act0 && n_c >= max(c0 - hs, 0) && n_c < min(c1 + hs, N);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int qr = rq[q], nr = rn[q];
+      if (nr >= rlo && nr < rhi && lact) {
+        const cpx<T> v = lval(qr, nr);
+        z[q] = mkc<T>(fmad(cs, v.re, rho[q].re), fmad(cs, v.im, rho[q].im));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int qr = rq[q], nr = rn[q];
+      if (nr >= rlo && nr < rhi && lact) buf[PAD + (qr * Wr + nr - wr0) * RS + lcol] = z[q];
+    }
+    __syncthreads();
+  }
+
+  // ---- final stage on the tile: rho' = rho + h L(Z3), compensated in float32 ----
+  const bool lact = act0 && n_c >= c0 && n_c < c1;
+  const bool comp = P.slo != nullptr;
+  cpx<T> zl[NR];
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    zl[q] = mkc<T>(0, 0);
+    {
+      const int qr = rq[q], nr = rn[q];
+      if (nr >= r0 && nr < r1 && lact) {
+        const cpx<T> v = lval(qr, nr);
+        const bool canon = !dtile || nr < n_c || (nr == n_c && qr <= qc);
+        const int i = qr * N + nr;
+        const long e = (long)i * d + jcol;
+        cpx<T> hi = rho[q], lo = mkc<T>(0, 0);
+        const cpx<T> dl = cscale(h, v);
+        if (comp) {
+          if (canon) lo = lo_at(P.slo, d, e);
+          two_sum_update(hi.re, lo.re, dl.re);
+          two_sum_update(hi.im, lo.im, dl.im);
+        } else {
+          hi = cadd(hi, dl);
+        }
+        if (i == jcol) {
+          hi.im = 0;
+          lo.im = 0;
+        }
+        z[q] = hi;
+        zl[q] = lo;
+        if (canon) {
+          bad |= !(isfinite(hi.re) && isfinite(hi.im));
+          P.ohi[e] = hi;
+          if (comp) lo_st(P.olo, e, lo);
+        }
+      }
+    }
+  }
+  if (bad) *status = 1;
+  // ---- conjugate mirror (j, i) of the canonical elements, through LDS ----
+  const int Tr = r1 - r0, Tc = c1 - c0;
+  const int nst = nq * nq * Tr * Tc;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    {
+      const int qr = rq[q], nr = rn[q];
+      if (nr >= r0 && nr < r1 && lact) {
+        // transposed staging: [q_c][n_c][q_r][n_r]
+        const int si = ((qc * Tc + n_c - c0) * nq + qr) * Tr + (nr - r0);
+        buf[si] = z[q];
+        if (comp) buf[nst + si] = zl[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (lane < nq * Tr) {
+    const int qr = lane / Tr;
+    const int nr = r0 + (lane - qr * Tr);
+    const int i = qr * N + nr;
+    for (int kk = wave; kk < nq * Tc; kk += NW) {
+      const int qcc = kk / Tc;
+      const int ncc = c0 + (kk - qcc * Tc);
+      const int j = qcc * N + ncc;
+      const bool canon = !dtile || nr < ncc || (nr == ncc && qr <= qcc);
+      if (canon && i != j) {
+        const int si = kk * nq * Tr + lane;
+        const long e = (long)j * d + i;
+        P.ohi[e] = conjg(buf[si]);
+        if (comp) lo_st(P.olo, e, conjg(buf[nst + si]));
+      }
+    }
+  }
+}
+
+// Batched launch: grid.x = B * ntile (the tiles of one problem on one XCD),
+// NW * 64 threads, dynamic LDS of fused_lds_elems(...) elements.
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void rk4_fused_kernel(BandOps<T> ops, FusedGeo g, StageIO<T> io, int d,
+                                                            const cpx<T>* __restrict__ coef, T h) {
+  extern __shared__ __align__(16) unsigned char fused_smem[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(fused_smem);
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / g.ntile, t = L - b * g.ntile;
+  rk4_fused_body<T, NW>(ops, g, resolve_strided(io, b), coef + (long)b * ops.nA * d, h, io.status, t, d, buf);
+}
+
+// Slot-table launch (continuous batching): request b of the launch reads
+// s_hi / s_lo of its table entry and writes o_hi / o_lo.  Up to MAXFSLOT
+// requests per launch (the table travels in the kernel arguments).
+constexpr int MAXFSLOT = 64;
+template <typename T>
+struct FusedSlot {
+  const cpx<T>* s_hi;
+  const cpx<T>* s_lo;
+  cpx<T>* o_hi;
+  cpx<T>* o_lo;
+  const cpx<T>* coef;  // diagonal coefficients of this request's slice
+};
+template <typename T>
+struct FusedSlotTable {
+  FusedSlot<T> e[MAXFSLOT];
+};
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void rk4_fused_slots_kernel(BandOps<T> ops, FusedGeo g,
+                                                                  FusedSlotTable<T> tab, T h, int* status, int d) {
+  extern __shared__ __align__(16) unsigned char fused_smem[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(fused_smem);
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = L / g.ntile, t = L - b * g.ntile;
+  const FusedSlot<T>& s = tab.e[b];
+  ProbPtr<T> P;
+  P.in = s.s_hi;
+  P.shi = s.s_hi;
+  P.slo = s.s_lo;
+  P.ohi = s.o_hi;
+  P.olo = s.o_lo;
+  P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
+  rk4_fused_body<T, NW>(ops, g, P, s.coef, h, status, t, d, buf);
+}
+
+// ---------------------------------------------------------------------------
 // Dense right-hand side epilogue: L(Y) = X + X^dag with X = A Y + 1/2 sum
 // gamma C Y C^dag already formed by the GEMMs; then the Runge-Kutta stage.
 // ---------------------------------------------------------------------------

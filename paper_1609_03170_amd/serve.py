@@ -5,16 +5,20 @@ sets (model shapes).  A request is admitted as soon as it has arrived and
 the HBM budget (the sum of the device bytes of the requests in flight) has
 room for it; every admitted request then advances together with the others
 of its shape in the batched launches of og_server_step, so requests that
-arrive while others run overlap with them on the device.  Completion time
-is taken after the stream work of the step that retired the request has
-finished; latency = completion - arrival.  The shapes' steps are issued
-from one host thread each (their launches go to separate streams and
-separate contexts), so the launch work of the host does not serialise them.
+arrive while others run overlap with them on the device.
+
+Every shape has its own server and stream; one host thread issues all of
+them.  A shape's next step is issued as soon as its previous one has
+finished on the device (a completion event per step; no device-wide
+synchronisation), so the shapes run side by side on the GPU.  Completion
+time is taken when the event of the step that retired the request has
+fired; latency = completion - arrival.  Controls are uploaded and checked on
+a separate admission stream, so admitting a request does not wait for the
+steps in flight.
 """
 from __future__ import annotations
 
 import time
-from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -57,18 +61,23 @@ class ServingLoop:
             self.sigma[key] = torch.tensor(w.sigma, device=self.device)
             self.rho0[key] = torch.tensor(w.rho0, device=self.device)
         self.dt = {key: w.dt for key, w in models.items()}
-        self._pool = ThreadPoolExecutor(max_workers=max(1, len(models)))
+        self.admit_stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.synchronize(self.device)  # operators and states uploaded before any step
 
     def close(self):
-        self._pool.shutdown(wait=True)
+        torch.cuda.synchronize(self.device)
         for s in self.servers.values():
             s.close()
         for p in self.problems.values():
             p.close()
 
-    def _step(self, key):
+    def _issue(self, key):
+        """Enqueue one step of shape `key` on its stream; returns its completion event."""
         with torch.cuda.device(self.device), torch.cuda.stream(self.streams[key]):
             self.servers[key].step(self.max_slices)
+            ev = torch.cuda.Event()
+            ev.record(self.streams[key])
+        return ev
 
     def run(self, requests, controls, *, time_scale=1.0, keep=False, log=None):
         """requests: list of dicts with keys id, shape, arrival (seconds,
@@ -76,7 +85,8 @@ class ServingLoop:
         pending = sorted(requests, key=lambda r: r["arrival"])
         out = Outcome()
         used = 0
-        inflight = {}  # tag -> (shape, bytes, arrival)
+        inflight = {}     # tag -> (shape, bytes, arrival)
+        running = {}      # shape -> completion event of its step in flight
         t0 = time.perf_counter()
         i = 0
         n_total = len(pending)
@@ -90,32 +100,50 @@ class ServingLoop:
                 need = srv.request_bytes(r["n_t"])
                 if used + need > self.budget and inflight:
                     break
-                with torch.cuda.stream(self.streams[key]):
+                with torch.cuda.device(self.device), torch.cuda.stream(self.admit_stream):
                     u = torch.tensor(controls(r), device=self.device)
                     if not srv.submit(r["id"], u, self.rho0[key], self.sigma[key], self.dt[key]):
                         break
+                    # the request's inputs and workspace are complete before its shape's stream uses them
+                    self.streams[key].wait_stream(self.admit_stream)
                 used += need
                 out.peak_bytes = max(out.peak_bytes, used)
                 inflight[r["id"]] = (key, need, r["arrival"] * time_scale)
                 i += 1
-            if not inflight:
-                if i < n_total:
-                    time.sleep(max(0.0, pending[i]["arrival"] * time_scale - (time.perf_counter() - t0)))
-                continue
-            active = [key for key, srv in self.servers.items() if srv.active]
-            list(self._pool.map(self._step, active))
-            torch.cuda.synchronize(self.device)
-            out.steps += 1
-            done_t = time.perf_counter() - t0
+            # retire the steps that have finished
+            progressed = False
+            for key in list(running):
+                if running[key].query():
+                    del running[key]
+                    progressed = True
+                    done_t = time.perf_counter() - t0
+                    for tag, res in self.servers[key].completed().items():
+                        k2, need, arr = inflight.pop(tag)
+                        used -= need
+                        out.latencies[tag] = done_t - arr
+                        if keep:
+                            out.results[tag] = res
+            # issue the next step of every shape that has work and no step in flight
             for key, srv in self.servers.items():
-                for tag, res in srv.completed().items():
-                    k2, need, arr = inflight.pop(tag)
-                    used -= need
-                    out.latencies[tag] = done_t - arr
-                    if keep:
-                        out.results[tag] = res
-            if log and out.steps % 200 == 0:
-                log(f"[serve] t={done_t:.1f}s done={len(out.latencies)}/{n_total} inflight={len(inflight)} "
-                    f"used={used / 2**30:.2f} GiB")
+                if key not in running and srv.active:
+                    running[key] = self._issue(key)
+                    out.steps += 1
+                    progressed = True
+                    if log and out.steps % 500 == 0:
+                        log(f"[serve] t={time.perf_counter() - t0:.1f}s done={len(out.latencies)}/{n_total} "
+                            f"inflight={len(inflight)} used={used / 2**30:.2f} GiB")
+            if progressed:
+                continue
+            if running:
+                # nothing to do on the host until the oldest step ends (or the next arrival)
+                ev = next(iter(running.values()))
+                if i < n_total:
+                    wait = pending[i]["arrival"] * time_scale - (time.perf_counter() - t0)
+                    if wait > 0.0005:
+                        time.sleep(min(wait, 0.0005))
+                        continue
+                ev.synchronize()
+            elif i < n_total:
+                time.sleep(max(0.0, pending[i]["arrival"] * time_scale - (time.perf_counter() - t0)))
         out.wall = time.perf_counter() - t0
         return out

@@ -26,6 +26,23 @@ def relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def grad_err(g, ref):
+    """Error of a gradient [..., N_t, K] against the oracle's: the largest of
+    the normwise relative error over all entries and that of every control
+    channel k (relative to the channel's own norm, floored at 1e-3 of the
+    whole gradient's norm for channels that are identically zero), so that a
+    channel with a small share of the norm (the qubit drives at d = 240) is
+    held to the same tolerance."""
+    g = np.asarray(g)
+    ref = np.asarray(ref)
+    total = max(np.linalg.norm(ref), 1e-300)
+    worst = float(np.linalg.norm(g - ref) / total)
+    for k in range(ref.shape[-1]):
+        den = max(np.linalg.norm(ref[..., k]), 1e-3 * total)
+        worst = max(worst, float(np.linalg.norm(g[..., k] - ref[..., k]) / den))
+    return worst
+
+
 def phi_err(phi, ref, sigma_norm=1.0):
     return abs(phi - ref) / max(abs(ref), 1e-3 * sigma_norm)
 

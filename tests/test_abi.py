@@ -83,6 +83,9 @@ def test_host_argument_errors_without_gpu():
     assert lib.og_set_adaptive(None, 1e-6, 1e-8) == -1
     assert lib.og_adaptive_stats(None, None) == -1
     assert lib.og_set_resident(None, 4) == -1
+    assert lib.og_generation(None) == 0
+    assert lib.og_set_fused(None, 1) == -1
+    assert lib.og_fused_used(None) == 0
 
 
 def test_create_banded_argument_errors_without_gpu():
@@ -152,4 +155,40 @@ def test_call_order_workspace_and_stability_errors():
     g = p.gradient()
     torch.cuda.synchronize()
     assert torch.isfinite(g).all()
+    p.close()
+
+
+@pytest.mark.gpu
+def test_setting_the_penalty_invalidates_the_forward_sweep():
+    """og_set_penalty changes the index (Eqs. (24)-(25)): the states recorded
+    by an earlier og_forward no longer belong to it, so og_cost and
+    og_adjoint refuse until the next forward sweep, which gives the penalised
+    value."""
+    import torch
+
+    from paper_1609_03170_amd import OgError, Problem
+    from oracle import extensions as ext
+    from oracle import rk
+
+    dev = torch.device("cuda", 0)
+    w = wl.config_c1()
+    p = Problem.from_workload(w)
+    u = torch.tensor(w.u[:12], device=dev)
+    r0 = torch.tensor(w.rho0, device=dev)
+    sigma = torch.tensor(w.sigma, device=dev)
+    g0 = p.generation
+    p.forward(u, r0, w.dt)
+    assert p.generation == g0 + 1
+    A = wl.destroy(10).conj().T @ wl.destroy(10)
+    p.set_penalty(A, 0.3)
+    for call in (lambda: p.cost(sigma), lambda: p.adjoint(sigma), lambda: p.gradient()):
+        with pytest.raises(OgError) as e:
+            call()
+        assert e.value.name == "OG_ERR_ORDER"
+    p.forward(u, r0, w.dt)
+    phi = p.cost(sigma)
+    torch.cuda.synchronize()
+    m = rk.Model.from_workload(w)
+    ref, _ = ext.penalty_cost(m, w.u[:12], w.rho0, w.sigma, A, 0.3, w.dt)
+    assert abs(float(phi.cpu()[0]) - ref) < 1e-12 * max(1.0, abs(ref))
     p.close()

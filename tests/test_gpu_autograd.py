@@ -110,3 +110,30 @@ def test_finite_differences_d240(n_t):
     say(f"   FD {np.array(fd)}\n   AD {got}")
     assert relerr(got, np.array(fd)) < 1e-7
     p.close()
+
+
+def test_two_applications_before_backward():
+    """loss = f(u1) + f(u2) on one Problem: the second forward sweep replaces
+    the first in the workspace; backward of the first application notices
+    (og_generation) and runs its forward sweep again, so both gradients are
+    the oracle's."""
+    import torch
+
+    from paper_1609_03170_amd import Problem, open_grape_cost
+
+    w = wl.config_c1()
+    u1_np, u2_np = w.u[:30], -0.5 * w.u[30:60]
+    say("[case] autograd C1 f64 exact, two applications then backward")
+    p = Problem.from_workload(w, prec="f64", gmode="exact")
+    u1 = torch.tensor(u1_np, device=_dev(), requires_grad=True)
+    u2 = torch.tensor(u2_np, device=_dev(), requires_grad=True)
+    rho0 = torch.tensor(w.rho0, device=_dev())
+    sigma = torch.tensor(w.sigma, device=_dev())
+    loss = open_grape_cost(u1, p, rho0, sigma, w.dt) + 2.0 * open_grape_cost(u2, p, rho0, sigma, w.dt)
+    loss.backward()
+    m = rk.Model.from_workload(w)
+    for u, u_np, wt in ((u1, u1_np, 1.0), (u2, u2_np, 2.0)):
+        rhos = rk.forward(m, u_np, w.rho0, w.dt)
+        g_ref, _ = rk.gradient_exact(m, u_np, rhos, w.sigma, w.dt)
+        assert relerr(u.grad.cpu().numpy(), wt * g_ref) < 1e-10
+    p.close()

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from _gpu_util import TOL, phi_err, relerr, say
+from _gpu_util import TOL, phi_err, grad_err, relerr, say
 from oracle import extensions as ext
 from oracle import rk
 
@@ -51,7 +51,7 @@ def test_penalty(prec, gmode, case):
     m = rk.Model.from_workload(w, sparse=sparse)
     phi_r, rhos = ext.penalty_cost(m, u, w.rho0, w.sigma, A, beta, w.dt)
     g_r = ext.penalty_gradient(m, u, rhos, w.sigma, A, beta, w.dt, mode=gmode)
-    e_phi, e_g = phi_err(phi, phi_r), relerr(g, g_r)
+    e_phi, e_g = phi_err(phi, phi_r), grad_err(g, g_r)
     say(f"   phi {e_phi:.2e} grad {e_g:.2e}")
     assert e_phi < TOL[prec]["phi"] and e_g < TOL[prec]["grad"]
 
@@ -80,7 +80,7 @@ def test_multi_state_two_contexts_and_batch(prec):
         p.close()
     ms = [rk.Model.from_workload(w) for w in ws]
     phi_r, g_r = ext.multi_state_cost_and_grad(ms, u, [w.rho0 for w in ws], vac, dt, mode="exact")
-    e_phi, e_g = phi_err(phi, phi_r), relerr(g.cpu().numpy(), g_r)
+    e_phi, e_g = phi_err(phi, phi_r), grad_err(g.cpu().numpy(), g_r)
     say(f"   phi {e_phi:.2e} grad {e_g:.2e}")
     assert e_phi < TOL[prec]["phi"] and e_g < TOL[prec]["grad"]
     # one context, three input states (coherent amplitudes 0.5, 1, 1.5)
@@ -93,7 +93,7 @@ def test_multi_state_two_contexts_and_batch(prec):
     gs = p.gradient_sum().cpu().numpy()
     p.close()
     ref = sum(rk.cost_and_grad(ms[0], u, r0, vac, dt)[1] for r0 in rho0s)
-    assert relerr(gs, ref) < TOL[prec]["grad"]
+    assert grad_err(gs, ref) < TOL[prec]["grad"]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from _gpu_util import TOL, gpu_eval, oracle_eval, phi_err, relerr, say
+from _gpu_util import TOL, gpu_eval, oracle_eval, phi_err, grad_err, relerr, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,7 @@ def _check(w, u, prec, path, gmode, n_sub=1, sparse=False, tag="", B_rho0=None, 
     tol = TOL[prec]
     for b in range(uu.shape[0]):
         phi_r, g_r, rho_r = oracle_eval(w, uu[b], mode=gmode, n_sub=n_sub, sparse=sparse)
-        e_rho, e_phi, e_g = relerr(rhoT[b], rho_r), phi_err(phi[b], phi_r), relerr(g[b], g_r)
+        e_rho, e_phi, e_g = relerr(rhoT[b], rho_r), phi_err(phi[b], phi_r), grad_err(g[b], g_r)
         say(f"   b={b} rho {e_rho:.2e} phi {e_phi:.2e} grad {e_g:.2e}")
         assert e_rho < tol["rho"]
         assert e_phi < tol["phi"]
@@ -79,7 +79,7 @@ def test_dense_split_precision_ragged_d70(prec, bound_phi, bound_g, gmode):
     p.close()
     for b in range(2):
         phi_r, g_r, rho_r = oracle_eval(w, u[b], mode=gmode)
-        e_phi, e_g, e_rho = phi_err(phi[b], phi_r), relerr(g[b], g_r), relerr(rhoT[b], rho_r)
+        e_phi, e_g, e_rho = phi_err(phi[b], phi_r), grad_err(g[b], g_r), relerr(rhoT[b], rho_r)
         say(f"   b={b} rho {e_rho:.2e} phi {e_phi:.2e} grad {e_g:.2e}")
         assert e_phi < bound_phi and e_g < bound_g
         assert np.array_equal(rhoT[b], rhoT[b].conj().T)

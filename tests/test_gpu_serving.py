@@ -5,12 +5,12 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from _gpu_util import relerr, say
+from _gpu_util import grad_err, relerr, say
 from oracle import rk
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = ((2, 10), (2, 20), (3, 30))
+SHAPES = wl.SERVING_SHAPES  # (n_q, N): d = 20, 40, 90, 160, 240
 
 
 def _trace(n, seed=3, n_t_range=(40, 130)):
@@ -32,7 +32,7 @@ def test_mix_matches_alone_and_oracle():
 
     from paper_1609_03170_amd import Problem
 
-    reqs = _trace(9)
+    reqs = _trace(10)  # two requests of every shape
     loop, models = _loop()
     say(f"[case] serving mix of {len(reqs)} requests, shapes {SHAPES}")
     out = loop.run(reqs, wl.serving_controls, keep=True)
@@ -55,10 +55,10 @@ def test_mix_matches_alone_and_oracle():
         assert abs(phi_b.cpu().numpy()[0] - phi_mix[0]) <= 1e-12 * max(1.0, abs(phi_mix[0]))
         assert relerr(g_mix, g_b.cpu().numpy()[0]) < 1e-12
         # float64 oracle
-        m = rk.Model.from_workload(w)
+        m = rk.Model.from_workload(w, sparse=True)
         phi_r, g_r, _ = rk.cost_and_grad(m, u, w.rho0, w.sigma, w.dt)
         e_phi = abs(phi_mix[0] - phi_r) / max(abs(phi_r), 1e-3)
-        e_g = relerr(g_mix, g_r)
+        e_g = grad_err(g_mix, g_r)
         say(f"   id={r['id']} shape={r['shape']} N_t={r['n_t']}: phi {e_phi:.2e} grad {e_g:.2e}")
         assert e_phi < 1e-5 and e_g < 1e-5
     loop.close()

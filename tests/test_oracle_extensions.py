@@ -107,6 +107,34 @@ def test_penalty_recursion_equals_sum_of_backward_evolutions():
     assert _relerr(g_pen, -w.dt * ref) < 1e-12
 
 
+@pytest.mark.parametrize("n_sub", [1, 2])
+def test_penalty_cost_value_closed_form(n_sub):
+    """The value of the penalised index (Eq. (24), with the integral of
+    Eq. (25) as the sum over n = 0 .. N of App. B), pinned by a closed form:
+    for the undriven damped resonator, Tr(a^dag a rho_n) = n0 P(-kappa h)^(n n_sub)
+    exactly in truncation (the adjoint generator maps a^dag a to -kappa a^dag a),
+    P the RK4 stability polynomial, so
+        Phi_p = dt n0 sum_{n=0}^{N} P(-kappa h)^(n n_sub).
+    A sum without the n = 0 term, one that stops at N - 1 or one without dt
+    misses it by at least 0.4 * dt * n0 * P^(N n_sub) (about 1e-2 here)."""
+    w = wl.config_c1()
+    m = rk.Model.from_workload(w)
+    n_t, beta = 37, 0.4
+    u = np.zeros((n_t, 2))
+    a = wl.destroy(10)
+    A = a.conj().T @ a
+    n0 = np.trace(A @ w.rho0).real
+    kappa = float(w.gammas[0])
+    z = -kappa * w.dt / n_sub
+    P = (1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24) ** n_sub
+    pen = w.dt * n0 * sum(P ** n for n in range(n_t + 1))
+    # sigma = I: Tr(rho_N) = 1 (the trace is conserved), so Phi = 1 - beta Phi_p
+    phi, rhos = ext.penalty_cost(m, u, w.rho0, np.eye(10, dtype=complex), A, beta, w.dt, n_sub)
+    assert len(rhos) == n_t + 1
+    assert abs(phi - (1.0 - beta * pen)) < 1e-13
+    assert beta * w.dt * n0 * P ** n_t > 1e-3
+
+
 def test_penalty_beta_zero_is_the_plain_index():
     w = wl.config_c1()
     m = rk.Model.from_workload(w)
