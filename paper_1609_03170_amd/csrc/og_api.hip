@@ -339,6 +339,13 @@ struct Engine : EngineBase {
   og::FusedGeo fgeo[2]{};
   size_t fused_lds[2] = {0, 0};
   static constexpr int kFusedNW = sizeof(T) == 4 ? 4 : 8;  // waves per block
+  // fused-step coefficient data per direction: A0 and A_k on the five
+  // diagonals (0, +1, -1, -N, +N) row by row (d x 5, K x d x 5), the row
+  // (d x 3) and column (d x FDR) factors of the dissipator taps
+  og::cpx<T>*fa0[2] = {nullptr, nullptr}, *fak[2] = {nullptr, nullptr};
+  og::cpx<T>*fdl[2] = {nullptr, nullptr}, *fdr[2] = {nullptr, nullptr};
+  og::cpx<T>* fcoef[2] = {nullptr, nullptr};  // ring of rows of FSLOT coefficients per slice
+  int fc0[2] = {0, 0}, fc1[2] = {0, 0};
   og::cpx<T>* HT = nullptr;    // dense: transposes of H_k, K x d x d
   int ntile = 0;
   static constexpr bool comp = sizeof(T) == 4;  // compensated states in float32
@@ -379,7 +386,7 @@ struct Engine : EngineBase {
     bool asc;
   } chint[2] = {{0, 0, true}, {0, 0, true}};
   void coef_hint(int dr, int lo, int hi, bool asc) { chint[dr] = CoefHint{lo, hi, asc}; }
-  void coef_reset() { cc0[0] = cc1[0] = cc0[1] = cc1[1] = 0; }
+  void coef_reset() { cc0[0] = cc1[0] = cc0[1] = cc1[1] = fc0[0] = fc1[0] = fc0[1] = fc1[1] = 0; }
   int max_nA() const { return std::max(dir[0].band.nA, dir[1].band.nA); }
   const og::cpx<T>* coef_ptr(int dr, int j) const {
     return acoef[dr] + (size_t)(j - cc0[dr]) * B * dir[dr].band.nA * d;
@@ -415,82 +422,119 @@ struct Engine : EngineBase {
     }
     if (hHd) (void)hipFree(hHd);
     if (HT) (void)hipFree(HT);
+    for (int s = 0; s < 2; ++s)
+      for (void* p : {(void*)fa0[s], (void*)fak[s], (void*)fdl[s], (void*)fdr[s]})
+        if (p) (void)hipFree(p);
   }
 
   // Structure test of the fused RK4 step (rk4_fused_kernel) for direction
-  // s, on the ladder-ordered diagonals offs (values a0, ak[k]) and dissipator
-  // taps (tp, tq, values dl, dr): offsets 0, +-1 and +-N with d = nq N, taps
-  // (0, 0), (s, s) with s = +-1 and (t, t) with t = +-N; the +-1 couplings
-  // must vanish between blocks of N (rows n = N - 1 for +1, n = 0 for -1),
-  // and the tile edge T must fit the lane mapping (nq (T + 6) <= 64) and
-  // the LDS (at most 64 KiB).  Otherwise the four-launch stage kernels run.
-  void fused_setup(int s, const std::vector<int>& offs, const std::vector<int>& tp, const std::vector<int>& tq,
-                   const std::vector<cd>& a0, const std::vector<std::vector<cd>>& ak,
-                   const std::vector<std::vector<cd>>& dl, const std::vector<std::vector<cd>>& dr) {
+  // s of the operators h, on the dissipator taps (tp, tq, values dl, dr) of
+  // the banded setup: diagonals of A(u) only at 0, +-1 and +-N with
+  // d = nq N, taps (0, 0), (s, s) with s = +-1 and (t N, t N) with t = +-1;
+  // the +-1 couplings must vanish between blocks of N (rows n = N - 1 for +1,
+  // n = 0 for -1); nq <= 4 and a tile edge T with nq (T + 6) <= 64 whose LDS
+  // needs fit in 64 KiB.  Then the coefficient data of the fused step are
+  // uploaded; otherwise the four-launch stage kernels run.
+  og_status fused_setup(int s, const DirHost& h, const std::vector<int>& tp, const std::vector<int>& tq,
+                        const std::vector<std::vector<cd>>& dl, const std::vector<std::vector<cd>>& dr) {
     fused[s] = false;
-    const og::BandOps<T>& ops = dir[s].band;
-    const int nA = (int)offs.size(), nD = (int)tp.size();
-    if (!ops.lad || nA > og::FMAXA || nD > og::FMAXD || nA < 3 || nD < 2) return;
-    if (offs[0] != 0 || offs[1] != 1 || offs[2] != -1 || tp[0] != 0 || tq[0] != 0) return;
-    if (tp[1] != tq[1] || (tp[1] != 1 && tp[1] != -1)) return;
-    int N = 0;  // block length from the offsets beyond 0, +-1 and the taps beyond (0,0), (s,s)
+    std::vector<int> offs;
+    collect_offsets(h.A0, offs);
+    for (auto& m : h.Ak) collect_offsets(m, offs);
+    int N = 0;  // block length from the diagonals beyond 0, +-1 and the taps beyond (0, 0), (+-1, +-1)
     auto take = [&](int o) {
       const int a = o < 0 ? -o : o;
       if (N == 0) N = a;
       return a == N;
     };
-    for (int a = 3; a < nA; ++a)
-      if (!take(offs[a])) return;
-    for (int t = 2; t < nD; ++t)
-      if (tp[t] != tq[t] || !take(tp[t])) return;
+    for (int o : offs)
+      if (o < -1 || o > 1)
+        if (!take(o)) return OG_OK;
+    int s1 = 0, t2 = 0, i0 = -1, i1 = -1, i2 = -1;
+    for (size_t t = 0; t < tp.size(); ++t) {
+      if (tp[t] != tq[t]) return OG_OK;
+      const int p = tp[t];
+      if (p == 0) {
+        if (i0 >= 0) return OG_OK;
+        i0 = (int)t;
+      } else if (p == 1 || p == -1) {
+        if (i1 >= 0) return OG_OK;
+        i1 = (int)t;
+        s1 = p;
+      } else {
+        if (i2 >= 0 || !take(p)) return OG_OK;
+        i2 = (int)t;
+        t2 = p > 0 ? 1 : -1;
+      }
+    }
     if (N == 0) N = d;
-    if (N < 2 || d % N != 0) return;
+    if (N < 2 || d % N != 0) return OG_OK;
     const int nq = d / N;
-    // no +-1 coupling across a block boundary (A(u) for every u, and the (s,s) tap)
+    if (nq > 4 || (nq == 1 && i2 >= 0)) return OG_OK;
+    if (s1 == 0) s1 = t2 != 0 ? t2 : 1;  // no (+-1, +-1) tap: a zero one
+    if (t2 != 0 && t2 != s1) return OG_OK;  // compiled for taps (s, s), (s N, s N) of one sign
+    if (t2 == 0 && nq > 1) t2 = s1;         // no (t N, t N) tap: a zero one
+    const int slot_off[5] = {0, 1, -1, -N, N};
+    std::vector<std::vector<cd>> a5;  // A0 and A_k on the five slots
+    a5.push_back(dia_values(h.A0, std::vector<int>(slot_off, slot_off + 5)));
+    for (auto& m : h.Ak) a5.push_back(dia_values(m, std::vector<int>(slot_off, slot_off + 5)));
+    // no +-1 coupling across a block boundary, for any u; none for the (s, s) tap
     for (int i = 0; i < d; ++i) {
       const int n = i % N;
-      if (n == N - 1) {
-        if (a0[(size_t)1 * d + i] != cd(0, 0)) return;
-        for (auto& v : ak)
-          if (v[(size_t)1 * d + i] != cd(0, 0)) return;
+      for (auto& v : a5) {
+        if (n == N - 1 && v[(size_t)1 * d + i] != cd(0, 0)) return OG_OK;
+        if (n == 0 && v[(size_t)2 * d + i] != cd(0, 0)) return OG_OK;
       }
-      if (n == 0) {
-        if (a0[(size_t)2 * d + i] != cd(0, 0)) return;
-        for (auto& v : ak)
-          if (v[(size_t)2 * d + i] != cd(0, 0)) return;
-      }
-      if ((tp[1] > 0 && n == N - 1) || (tp[1] < 0 && n == 0))
-        if (dl[1][i] != cd(0, 0) || dr[1][i] != cd(0, 0)) return;
+      if (i1 >= 0 && ((s1 > 0 && n == N - 1) || (s1 < 0 && n == 0)))
+        if (dl[i1][i] != cd(0, 0) || dr[i1][i] != cd(0, 0)) return OG_OK;
     }
-    // tile edge: the widest that fits the lanes and the LDS
+    // tile edge: the widest that fits the lanes (nq (T + 6) <= 64), the
+    // compiled LDS stride (window edge min(T + 8, N) <= WS) and 64 KiB of LDS
+    const int ws = nq == 1 ? og::fused_ws<T, 1>() : nq == 2 ? og::fused_ws<T, 2>()
+                 : nq == 3 ? og::fused_ws<T, 3>() : og::fused_ws<T, 4>();
     const int tlane = 64 / nq - 6;
-    if (tlane < 2) return;
-    for (int nb = (N + tlane - 1) / tlane; nb <= N; ++nb) {
+    int nb = (N + tlane - 1) / tlane;
+    size_t bytes = 0;
+    for (; nb <= N; ++nb) {
       const int tmax = (N + nb - 1) / nb;
-      const int wmax = std::min(tmax + 8, N);
-      const size_t bytes = (size_t)og::fused_lds_elems(nq, wmax, tmax) * sizeof(og::cpx<T>);
-      if (bytes > 65536) continue;
-      og::FusedGeo& g = fgeo[s];
-      g = og::FusedGeo{};
-      g.N = N;
-      g.nq = nq;
-      g.nb = nb;
-      g.ntile = nb * (nb + 1) / 2;
-      g.nA = nA;
-      g.nD = nD;
-      auto split = [&](int o, int& q, int& n) {
-        q = (o == N) ? 1 : (o == -N ? -1 : 0);
-        n = q != 0 ? 0 : o;
-      };
-      for (int a = 0; a < nA; ++a) split(offs[a], g.aq[a], g.an[a]);
-      for (int t = 0; t < nD; ++t) split(tp[t], g.tq[t], g.tn[t]);
-      if (nq == 1) {  // N = d: no q couplings; offsets +-1 are n steps
-        for (int a = 0; a < nA; ++a) g.aq[a] = 0, g.an[a] = offs[a];
-      }
-      fused_lds[s] = bytes;
-      fused[s] = true;
-      return;
+      bytes = (size_t)og::fused_lds_elems(nq, ws, tmax) * sizeof(og::cpx<T>);
+      if (std::min(tmax + 8, N) <= ws && bytes <= 65536) break;
     }
+    if (nb > N || (N + nb - 1) / nb < 2) return OG_OK;
+    // coefficient data, row by row
+    std::vector<cd> a0t((size_t)d * 5), akt((size_t)K * d * 5), dlt((size_t)d * 3, cd(0, 0));
+    std::vector<cd> drt((size_t)d * og::FDR, cd(0, 0));
+    for (size_t m = 0; m < a5.size(); ++m)
+      for (int i = 0; i < d; ++i)
+        for (int a = 0; a < 5; ++a) {
+          const cd v = a5[m][(size_t)a * d + i];
+          if (m == 0)
+            a0t[(size_t)i * 5 + a] = v;
+          else
+            akt[((m - 1) * (size_t)d + i) * 5 + a] = v;
+        }
+    const int idx[3] = {i0, i1, i2};
+    for (int t = 0; t < 3; ++t)
+      if (idx[t] >= 0)
+        for (int i = 0; i < d; ++i) {
+          dlt[(size_t)i * 3 + t] = dl[idx[t]][i];
+          drt[(size_t)i * og::FDR + t] = dr[idx[t]][i];
+        }
+    OG_TRY(upload<T>(a0t, &fa0[s]));
+    OG_TRY(upload<T>(akt, &fak[s]));
+    OG_TRY(upload<T>(dlt, &fdl[s]));
+    OG_TRY(upload<T>(drt, &fdr[s]));
+    og::FusedGeo& g = fgeo[s];
+    g = og::FusedGeo{};
+    g.N = N;
+    g.nq = nq;
+    g.nb = nb;
+    g.ntile = nb * (nb + 1) / 2;
+    g.s1 = s1;
+    g.t2 = t2;
+    fused_lds[s] = bytes;
+    fused[s] = true;
+    return OG_OK;
   }
 
   og_status init(const DirHost host[2], const std::vector<Mat>& Hk) {
@@ -541,7 +585,7 @@ struct Engine : EngineBase {
         dv.band.Ak = dv.bAk;
         dv.band.Dl = dv.bDl;
         dv.band.Dr = dv.bDr;
-        fused_setup(s, offs, tp, tq, dia_values(h.A0, offs), ak, dl, dr);
+        OG_TRY(fused_setup(s, h, tp, tq, dl, dr));
       } else {
         OG_TRY(upload<T>(h.A0.a, &dv.A0));
         std::vector<std::vector<cd>> ak, cc, ch;
@@ -582,7 +626,7 @@ struct Engine : EngineBase {
   enum {
     L_CUR_HI, L_CUR_LO, L_LAM_HI, L_LAM_LO, L_ZA, L_ZB, L_CK_HI, L_CK_LO, L_SG_HI, L_SG_LO,
     L_Z1, L_Z2, L_Z3, L_ZB1, L_ZB2, L_ZB3, L_ST_HI, L_ST_LO, L_AJF, L_AJA, L_X, L_W, L_WP, L_PS, L_COEF, L_GRAD, L_PEN,
-    L_DPK, L_DPY, L_DPD, L_DPP, L_DPC, L_DPCK, L_TAIL, L_N
+    L_DPK, L_DPY, L_DPD, L_DPP, L_DPC, L_DPCK, L_TAIL, L_FCOEF, L_N
   };
   static_assert(L_N <= kMaxRegions, "workspace layout has more regions than Layout holds");
 
@@ -650,6 +694,8 @@ struct Engine : EngineBase {
       sz[L_DPCK] = (size_t)nseg * b * 2 * sizeof(double);
     }
     sz[L_TAIL] = ntail > 0 ? (size_t)(ntail + 1) * m : 0;
+    if (banded && (fused[0] || fused[1]))
+      sz[L_FCOEF] = 2 * (size_t)kCoefChunk * b * og::FSLOT * d * sizeof(og::cpx<T>);
     size_t pos = 0;
     for (int i = 0; i < L_N; ++i) {
       L.off[i] = pos;
@@ -847,6 +893,25 @@ struct Engine : EngineBase {
   }
 
   bool use_fused(int dr) const { return banded && fused[dr] && ctx->fused_on; }
+
+  // Call f(levels, sign) with the compile-time level count (1..4) and tap
+  // sign (+-1) of direction dr's fused step.
+  template <typename F>
+  void fused_dispatch(int dr, F&& f) {
+    using std::integral_constant;
+    const int nq = fgeo[dr].nq, sg = fgeo[dr].s1;
+    if (sg > 0) {
+      if (nq == 1) f(integral_constant<int, 1>{}, integral_constant<int, 1>{});
+      else if (nq == 2) f(integral_constant<int, 2>{}, integral_constant<int, 1>{});
+      else if (nq == 3) f(integral_constant<int, 3>{}, integral_constant<int, 1>{});
+      else f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
+    } else {
+      if (nq == 1) f(integral_constant<int, 1>{}, integral_constant<int, -1>{});
+      else if (nq == 2) f(integral_constant<int, 2>{}, integral_constant<int, -1>{});
+      else if (nq == 3) f(integral_constant<int, 3>{}, integral_constant<int, -1>{});
+      else f(integral_constant<int, 4>{}, integral_constant<int, -1>{});
+    }
+  }
   int fused_used() const override { return use_fused(FWD) && use_fused(ADJ) ? 1 : 0; }
 
   // One fused RK4 step (the four nested stages in one launch) for the whole
@@ -855,17 +920,42 @@ struct Engine : EngineBase {
   // ilo (every element's compensation term is read and written by one block).
   og_status fused_step(int dr, int jslice, const og::cpx<T>* ihi, const og::cpx<T>* ilo, og::cpx<T>* ohi,
                        og::cpx<T>* olo, T h) {
+    OG_TRY(assemble_fused(dr, jslice));
     og::StageIO<T> io = io_base();
     io.in = ihi;
     io.shi = ihi;
     io.slo = ilo;
     io.ohi = ohi;
     io.olo = olo;
+    const og::cpx<T>* cf = fcoef[dr] + (size_t)(jslice - fc0[dr]) * B * og::FSLOT * d;
+    const dim3 grid((unsigned)(B * fgeo[dr].ntile));
     const long pidx = ctx->prof_begin(st);
-    og::rk4_fused_kernel<T, kFusedNW><<<dim3((unsigned)(B * fgeo[dr].ntile)), kFusedNW * 64, fused_lds[dr], st>>>(
-        dir[dr].band, fgeo[dr], io, d, coef_ptr(dr, jslice), h);
+    fused_dispatch(dr, [&](auto nq, auto sg) {
+      og::rk4_fused_kernel<T, decltype(nq)::value, kFusedNW, decltype(sg)::value>
+          <<<grid, kFusedNW * 64, fused_lds[dr], st>>>(fgeo[dr], io, d, cf, fdr[dr], h);
+    });
     OG_CHECK_LAUNCH();
     ctx->prof_end(pidx, st);
+    return OG_OK;
+  }
+
+  // Coefficients of the fused step (rows of FSLOT) for slice j of direction
+  // dr: when j is not in the held chunk, the next kCoefChunk slices in the
+  // direction of the current sweep (the same hints as the stage kernels'
+  // coefficients) are computed at once.
+  og_status assemble_fused(int dr, int jslice) {
+    if (jslice >= fc0[dr] && jslice < fc1[dr]) return OG_OK;
+    const CoefHint& hn = chint[dr];
+    const int lo = std::max(0, std::min(hn.lo, jslice)), hi = std::min(n_t, std::max(hn.hi, jslice + 1));
+    const int c0 = hn.asc ? jslice : std::max(lo, jslice - kCoefChunk + 1);
+    const int c1 = hn.asc ? std::min(hi, jslice + kCoefChunk) : jslice + 1;
+    const int n = og::FSLOT * d;
+    const unsigned gx = (unsigned)std::max(1, std::min((n + 255) / 256, 64));
+    og::fused_coef_kernel<T><<<dim3(gx, (unsigned)B, (unsigned)(c1 - c0)), 256, 0, st>>>(
+        fa0[dr], fak[dr], fdl[dr], d, K, u, (long)n_t * K, c0, fcoef[dr]);
+    OG_CHECK_LAUNCH();
+    fc0[dr] = c0;
+    fc1[dr] = c1;
     return OG_OK;
   }
 
@@ -876,7 +966,6 @@ struct Engine : EngineBase {
     if (!use_fused(dr)) return rk_slice(dr, jslice, hi, lo, hi, lo);
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dt / nsub);
-    OG_TRY(assemble(dr, jslice));
     for (int s = 0; s < nsub; ++s) {
       OG_TRY(fused_step(dr, jslice, hi, lo, alt, lo, h));
       std::swap(hi, alt);
@@ -892,7 +981,6 @@ struct Engine : EngineBase {
                      og::cpx<T>* olo) {
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dt / nsub);
-    OG_TRY(assemble(dr, jslice));
     if (use_fused(dr)) {
       if (ihi == ohi) return fail(OG_ERR_ARG, "internal: fused RK4 step in place");
       const og::cpx<T>* src = ihi;
@@ -905,6 +993,7 @@ struct Engine : EngineBase {
       }
       return OG_OK;
     }
+    OG_TRY(assemble(dr, jslice));
     for (int s = 0; s < nsub; ++s) {
       const og::cpx<T>* shi = s == 0 ? ihi : ohi;
       const og::cpx<T>* slo = s == 0 ? ilo : olo;
@@ -1112,6 +1201,8 @@ struct Engine : EngineBase {
     Ps = opt_at(L_PS, !banded && J > 0 && J <= og::GM);
     acoef[0] = opt_at(L_COEF, banded);
     acoef[1] = banded ? acoef[0] + (size_t)kCoefChunk * b * max_nA() * d : nullptr;
+    fcoef[0] = opt_at(L_FCOEF, banded && (fused[0] || fused[1]));
+    fcoef[1] = fcoef[0] ? fcoef[0] + (size_t)kCoefChunk * b * og::FSLOT * d : nullptr;
     grad = reinterpret_cast<double*>(p + L.off[L_GRAD]);
     if (ctx->ad_rtol > 0.0) {
       dpk = at(L_DPK);
@@ -1473,16 +1564,29 @@ struct Engine : EngineBase {
           og::band_contract_slots_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
         OG_CHECK_LAUNCH();
       }
-      og::SlotTable<T> ct{};
-      for (int q = 0; q < m; ++q) {
-        const Op& o = ops[i0 + q0 + q];
-        const Slot& sl = slots[o.slot];
-        ct.e[q].coef = dr == FWD ? sl.coefF : sl.coefA;
-        ct.e[q].urow = sl.r.u + (long)o.slice * K;
+      if (use_fused(dr)) {
+        og::FusedCoefSlots<T> ct{};
+        for (int q = 0; q < m; ++q) {
+          const Op& o = ops[i0 + q0 + q];
+          const Slot& sl = slots[o.slot];
+          ct.coef[q] = dr == FWD ? sl.coefF : sl.coefA;
+          ct.urow[q] = sl.r.u + (long)o.slice * K;
+        }
+        const int na = og::FSLOT * d;
+        const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
+        og::fused_coef_slots_kernel<T><<<dim3(gx, (unsigned)m), 256, 0, st>>>(fa0[dr], fak[dr], fdl[dr], d, K, ct);
+      } else {
+        og::SlotTable<T> ct{};
+        for (int q = 0; q < m; ++q) {
+          const Op& o = ops[i0 + q0 + q];
+          const Slot& sl = slots[o.slot];
+          ct.e[q].coef = dr == FWD ? sl.coefF : sl.coefA;
+          ct.e[q].urow = sl.r.u + (long)o.slice * K;
+        }
+        const int na = dir[dr].band.nA * d;
+        const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
+        og::band_coef_slots_kernel<T><<<dim3(gx, (unsigned)m), 256, 0, st>>>(dir[dr].band, ct, d, K);
       }
-      const int na = dir[dr].band.nA * d;
-      const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
-      og::band_coef_slots_kernel<T><<<dim3(gx, (unsigned)m), 256, 0, st>>>(dir[dr].band, ct, d, K);
       OG_CHECK_LAUNCH();
     }
     const int nsub = ctx->opt.n_sub;
@@ -1515,10 +1619,12 @@ struct Engine : EngineBase {
             prev[q] = e.o_hi;
           }
         }
+        const dim3 grid((unsigned)(n * fgeo[dr].ntile));
         const long pidx = ctx->prof_begin(st);
-        og::rk4_fused_slots_kernel<T, kFusedNW><<<dim3((unsigned)(n * fgeo[dr].ntile)), kFusedNW * 64,
-                                                 fused_lds[dr], st>>>(dir[dr].band, fgeo[dr], ft, h,
-                                                                      ctx->status_dev, d);
+        fused_dispatch(dr, [&](auto nq, auto sg) {
+          og::rk4_fused_slots_kernel<T, decltype(nq)::value, kFusedNW, decltype(sg)::value>
+              <<<grid, kFusedNW * 64, fused_lds[dr], st>>>(fgeo[dr], ft, fdr[dr], h, ctx->status_dev, d);
+        });
         OG_CHECK_LAUNCH();
         ctx->prof_end(pidx, st);
       }

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace og {
 
 constexpr int TS = 32;      // tile edge of the stage / epilogue kernels
@@ -62,6 +64,20 @@ __device__ __forceinline__ void cfmac(cpx<T>& acc, cpx<T> a, cpx<T> b) {
 template <typename T>
 __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
   return mkc<T>(fmad(a.re, b.re, a.im * b.im), fmad(a.im, b.re, -(a.re * b.im)));
+}
+
+// f(std::integral_constant<int, i>) for i = 0 .. n - 1 (an unrolled loop
+// whose index is a compile-time constant in the body).
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for_from(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_from<I + 1, N>(f);
+  }
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_from<0, N>(f);
 }
 
 // Map the hardware block id to a logical one so that consecutive logical
@@ -687,13 +703,13 @@ __global__ __launch_bounds__(TS * TS / SlotCfg<T>::NQ) void band_stage_slots_ker
 // Fused Runge-Kutta step: the four nested stages of one RK4 step (Horner
 // form Z1 = rho + h/4 L(rho), Z2 = rho + h/3 L(Z1), Z3 = rho + h/2 L(Z2),
 // rho' = rho + h L(Z3)) in one launch, for operators with the structure of
-// a multi-level system of nq levels coupled to an oscillator of N levels
-// (the transmon x resonator models of Sec. IV): d = nq N, index i = q N + n;
-// A(u) has diagonals at offsets 0, +-1 (never linking one block of N to the
-// next) and +-N; the dissipator taps are (0, 0), (s, s) with s = +-1, and
-// (t, t) with t = +-N.  One stage of L then reaches one step in n and one
+// a multi-level system of NQ levels coupled to an oscillator of N levels
+// (the transmon x resonator models of Sec. IV): d = NQ N, index i = q N + n;
+// A(u) has diagonals at offsets 0, +1, -1 (never linking one block of N to
+// the next), -N, +N; the dissipator taps are (0, 0), (s, s) with s = +-1 and
+// (t N, t N) with t = +-1.  One stage of L then reaches one step in n and one
 // step in q.  A block computes the step on one tile of n-ranges
-// [r0, r1) x [c0, c1) for all nq x nq level pairs, so the q-couplings stay
+// [r0, r1) x [c0, c1) for all NQ x NQ level pairs, so the q-couplings stay
 // inside the tile and the n-halo grows by one per stage: the tile and a halo
 // of 4 in n are read from global memory into LDS once, the stages run on
 // shrinking regions of it (halo 3, 2, 1, then the tile itself), and only
@@ -708,27 +724,30 @@ __global__ __launch_bounds__(TS * TS / SlotCfg<T>::NQ) void band_stage_slots_ker
 // are not made so.
 //
 // Work mapping: lane l of every wave owns one column (q_c, n_c) of the
-// stage-0 region (nq (T + 6) <= 64 columns, T the tile edge); wave w owns
-// the rows w, w + NW, ... of the stage-0 region, so the row index and the
-// row coefficients of A(u) and of the dissipators are wave-uniform (scalar
-// loads) and the column coefficients stay in registers.  The state rho of a
-// thread's elements stays in registers across the stages; a stage's outputs
-// are held in registers until every wave has read the stage input, then
-// written over it (one LDS buffer).  Taps that would leave the window or the
-// matrix have zero coefficients (checked on the host); their LDS addresses
-// stay inside the buffer (zero-filled pads of one row and one element at
-// both ends) or are redirected to the element itself.
+// stage-0 region (NQ (T + 6) <= 64 columns, T the tile edge); wave w owns
+// the rows n = w, w + NW, ... of every level, so a row and its coefficients
+// are wave-uniform: the eight coefficients of a row (the five diagonals of
+// A(u) and the three row factors gamma C[i, i + p] of the dissipator taps)
+// are stored together and fetched by one scalar load.  The column
+// coefficients stay in registers.  The state rho of a thread's elements
+// stays in registers across the stages; a stage's outputs are held in
+// registers until every wave has read the stage input, then written over it
+// (one LDS buffer).  Every lane computes (lanes outside the stage's region
+// on a clamped column) and stores to a scratch slot when it is outside, so
+// the stages run without divergent branches.  Taps that would leave the
+// window or the matrix have zero coefficients (checked on the host); their
+// LDS addresses stay inside the buffer (zero-filled pads of one row and one
+// element at both ends) or are redirected to the element itself.
 // ---------------------------------------------------------------------------
-constexpr int FMAXA = 5;  // diagonals: 0, +1, -1, +N, -N
-constexpr int FMAXD = 3;  // dissipator taps: (0, 0), (s, s), (t, t)
+constexpr int FSLOT = 8;  // coefficients per row: A(u) at 0, +1, -1, -N, +N; dissipator rows 0, s, t
+constexpr int FDR = 4;    // dissipator column factors per column (three used)
 
 struct FusedGeo {
-  int N, nq;                 // d = nq N
-  int nb;                    // n-blocks per axis; block k is [k N / nb, (k + 1) N / nb)
-  int ntile;                 // nb (nb + 1) / 2 tiles per problem
-  int nA, nD;                // diagonals / dissipator taps in use (ladder order)
-  int aq[FMAXA], an[FMAXA];  // diagonal a: offset aq N + an
-  int tq[FMAXD], tn[FMAXD];  // dissipator tap t: (p, p) with p = tq N + tn
+  int N, nq;   // d = nq N
+  int nb;      // n-blocks per axis; block k is [k N / nb, (k + 1) N / nb)
+  int ntile;   // nb (nb + 1) / 2 tiles per problem
+  int s1;      // tap (s, s): s = s1 (+-1)
+  int t2;      // tap (t N, t N): t = t2 (+-1), 0 without it
 };
 
 // (row block, column block) of upper tile t of an nb x nb grid, row-major.
@@ -741,121 +760,206 @@ __device__ __forceinline__ int2 fused_tile(int t, int nb) {
   return make_int2(r, r + t);
 }
 
-// LDS elements (cpx<T>) the fused step needs for a window of at most
-// wmax x wmax per level pair: the window with its pads, or the staging of
-// the tile's new state (hi and lo) for the transposed write, if larger.
-__host__ __device__ __forceinline__ int fused_lds_elems(int nq, int wmax, int tmax) {
-  const int win = nq * nq * wmax * wmax + 2 * (nq * wmax + 1);
-  const int stg = 2 * nq * nq * tmax * tmax;
+
+// Coefficients of the fused step for slices jslice .. jslice + gridDim.z - 1
+// and every problem b (gridDim.y): out[z][b][i][FSLOT] = the diagonals of
+// A(u_j) = A0 + sum_k u[b, j, k] Ak at row i (slots 0..4) and the row
+// factors of the dissipator taps (slots 5..7, constant).
+template <typename T>
+__global__ __launch_bounds__(256) void fused_coef_kernel(const cpx<T>* __restrict__ a0, const cpx<T>* __restrict__ ak,
+                                                         const cpx<T>* __restrict__ dl, int d, int K,
+                                                         const double* __restrict__ u, long u_bs, int jslice,
+                                                         cpx<T>* __restrict__ coef) {
+  const int b = blockIdx.y, z = blockIdx.z;
+  const double* ub = u + (long)b * u_bs + (long)(jslice + z) * K;
+  cpx<T>* out = coef + ((long)z * gridDim.y + b) * FSLOT * d;
+  const int n = FSLOT * d;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int i = e / FSLOT, a = e - i * FSLOT;
+    cpx<T> v;
+    if (a < 5) {
+      v = a0[i * 5 + a];
+      for (int k = 0; k < K; ++k) {
+        const T uk = (T)ub[k];
+        const cpx<T> h = ak[((long)k * d + i) * 5 + a];
+        v.re += uk * h.re;
+        v.im += uk * h.im;
+      }
+    } else {
+      v = dl[i * 3 + (a - 5)];
+    }
+    out[e] = v;
+  }
+}
+
+// LDS window edge of the fused step (rows and columns of n per level pair):
+// the widest T + 8 whose buffer fits in 64 KiB, with T + 6 <= 64 / NQ (the
+// lane mapping).  It is compile-time, so every tap of the stencil is an
+// immediate offset of one LDS address per row.
+template <typename T, int NQ>
+constexpr int fused_ws() {
+  return sizeof(T) == 4 ? (NQ == 1 ? 66 : NQ == 2 ? 34 : NQ == 3 ? 22 : 18)
+                        : (NQ == 1 ? 61 : NQ == 2 ? 30 : NQ == 3 ? 20 : 15);
+}
+
+// Odd stride (in elements) of the staging of the tile's new state, so that
+// the lanes' 8- or 16-byte stores to it fall in distinct LDS banks.
+__host__ __device__ __forceinline__ int fused_stage_stride(int nq, int tr) { return (nq * tr) | 1; }
+
+// LDS elements (cpx<T>) of the fused step: the window (NQ^2 WS^2) with its
+// pads (one row and one column at both ends) and 64 scratch slots, or the
+// staging of the tile's new state (hi and lo) for the transposed write, if
+// larger (tmax: the largest tile edge).
+__host__ __device__ __forceinline__ int fused_lds_elems(int nq, int ws, int tmax) {
+  const int win = nq * nq * ws * ws + 2 * (nq * ws + nq) + 64;
+  const int stg = 2 * nq * tmax * fused_stage_stride(nq, tmax);
   return win > stg ? win : stg;
 }
 
-template <typename T, int NW>
-__device__ __forceinline__ void rk4_fused_body(const BandOps<T>& ops, const FusedGeo& g, const ProbPtr<T>& P,
-                                               const cpx<T>* __restrict__ cb, T h, int* status, int t, int d,
-                                               cpx<T>* __restrict__ buf) {
-  constexpr int NR = 64 / NW;  // stage-0 rows per wave: nq (T + 6) <= 64 rows in all
+template <typename T, int NQ, int NW, int S>
+__device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<T>& P,
+                                               const cpx<T>* __restrict__ cb, const cpx<T>* __restrict__ drt,
+                                               T h, int* status, int t, int d, cpx<T>* __restrict__ buf) {
+  // LDS layout: element (q_r, n_r; q_c, n_c) of the window at
+  //   PAD + (q_r WS + n_r - wr0) RS + (n_c - wc0) NQ + q_c,
+  // levels of the column innermost, so the lanes of a row read and write
+  // consecutive elements.
+  constexpr int WS = fused_ws<T, NQ>();
+  constexpr int RS = NQ * WS;    // LDS stride of one row (q_r, n_r)
+  constexpr int QS = WS * RS;    // LDS stride of one level q_r
+  constexpr int PAD = RS + NQ;   // the largest tap offset: one row and one column
+  constexpr int NWIN = NQ * QS;
+  constexpr int MM = (WS - 2 + NW - 1) / NW;  // rows per level per wave (h0 <= T + 6 <= WS - 2)
+  constexpr int NS = NQ * MM;                 // row slots per wave
+  constexpr int LOW = QS + RS + NQ;           // most negative tap offset, bounded
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int N = g.N, nq = g.nq, nb = g.nb, nA = g.nA, nD = g.nD;
+  const int N = g.N, nb = g.nb;
   const int2 tb = fused_tile(t, nb);
   const bool dtile = tb.x == tb.y;
   const int r0 = tb.x * N / nb, r1 = (tb.x + 1) * N / nb;
   const int c0 = tb.y * N / nb, c1 = (tb.y + 1) * N / nb;
-  // window: the tile with a halo of 4 in n, clipped to [0, N)
+  // window: the tile with a halo of 4 in n, clipped to [0, N); Wr, Wc <= WS
   const int wr0 = max(r0 - 4, 0), Wr = min(r1 + 4, N) - wr0;
   const int wc0 = max(c0 - 4, 0), Wc = min(c1 + 4, N) - wc0;
-  const int RS = nq * Wc;   // LDS stride of one row (q_r, n_r)
-  const int QS = Wr * RS;   // LDS stride of one level q_r
-  const int PAD = RS + 1;
-  const int nwin = nq * QS;
+  const int scratch = PAD + NWIN + PAD + lane;  // this lane's slot for stores outside the region
   // stage-0 output region: halo 3
   const int rs0 = max(r0 - 3, 0), h0 = min(r1 + 3, N) - rs0;
   const int cs0 = max(c0 - 3, 0), w0 = min(c1 + 3, N) - cs0;
-  const int nrow0 = nq * h0;
   const cpx<T>* __restrict__ Y = P.in;
 
-  // ---- window -> LDS (rows by wave, columns by lane; two lane passes) ----
+  // ---- window -> LDS: rows by wave, columns by lane (two lane passes).
+  // Every cell of the WS x WS block of each level pair is written: the
+  // window's elements, zeros beyond it (read only by taps with zero
+  // coefficients at the ends of the n range). ----
   {
-    int goff[2], ok[2];
+    int goff[2];
+    bool inw[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const int c = lane + 64 * p;
-      ok[p] = c < RS;
-      const int qc = ok[p] ? c / Wc : 0;
-      goff[p] = qc * N + wc0 + (c - qc * Wc);
+      const int c = lane + 64 * p;  // LDS column within the row: (n - wc0) NQ + qc
+      const int cn = c / NQ, qc = c - cn * NQ;
+      inw[p] = c < RS && cn < Wc;
+      goff[p] = qc * N + wc0 + cn;
     }
-    for (int k = wave; k < nq * Wr; k += NW) {
-      const int qr = k / Wr;
-      const unsigned grow = __umul24(qr * N + wr0 + (k - qr * Wr), d);
+    constexpr int MW = (WS + NW - 1) / NW;  // LDS rows per level per wave
+    cpx<T> v[NQ][MW][2];
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
-        if (ok[p]) buf[PAD + k * RS + lane + 64 * p] = ldm(Y, grow + goff[p]);
-    }
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int m = 0; m < MW; ++m) {
+        const int nr = wave + NW * m;
+        const unsigned grow = __umul24(q * N + wr0 + nr, d);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) v[q][m][p] = (nr < Wr && inw[p]) ? ldm(Y, grow + goff[p]) : mkc<T>(0, 0);
+      }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int m = 0; m < MW; ++m) {
+        const int nr = wave + NW * m;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          if (nr < WS && lane + 64 * p < RS) buf[PAD + (q * WS + nr) * RS + lane + 64 * p] = v[q][m][p];
+      }
     for (int e = tid; e < PAD; e += 64 * NW) {
       buf[e] = mkc<T>(0, 0);
-      buf[PAD + nwin + e] = mkc<T>(0, 0);
+      buf[PAD + NWIN + e] = mkc<T>(0, 0);
     }
   }
 
-  // ---- this lane's column ----
-  const bool act0 = lane < nq * w0;
-  const int qc = act0 ? lane / w0 : 0;
-  const int n_c = cs0 + (lane - qc * w0);
+  // ---- this lane's column (lanes beyond the region compute on the last one) ----
+  const bool act0 = lane < NQ * w0;
+  const int lc = act0 ? lane : NQ * w0 - 1;
+  const int cn0 = lc / NQ, qc = lc - cn0 * NQ;
+  const int n_c = cs0 + cn0;
   const int jcol = qc * N + n_c;
-  const int lcol = qc * Wc + (n_c - wc0);
-  cpx<T> cC[FMAXA], dC[FMAXD];
+  const int lcol = PAD + (n_c - wc0) * NQ + qc - wr0 * RS;  // + (q WS + n_r) RS: the element's LDS index
+  cpx<T> cC[5], dC[3];
 #pragma unroll
-  for (int a = 0; a < FMAXA; ++a) cC[a] = (act0 && a < nA) ? cb[a * d + jcol] : mkc<T>(0, 0);
+  for (int a = 0; a < 5; ++a) cC[a] = cb[jcol * FSLOT + a];
 #pragma unroll
-  for (int s = 0; s < FMAXD; ++s) dC[s] = (act0 && s < nD) ? ops.Dr[s * d + jcol] : mkc<T>(0, 0);
-  int dCa[FMAXA], dCt[FMAXD];
-#pragma unroll
-  for (int a = 0; a < FMAXA; ++a) dCa[a] = a < nA ? g.aq[a] * Wc + g.an[a] : 0;
-#pragma unroll
-  for (int s = 0; s < FMAXD; ++s) dCt[s] = s < nD ? g.tq[s] * Wc + g.tn[s] : 0;
+  for (int s = 0; s < 3; ++s) dC[s] = drt[jcol * FDR + s];
 
   __syncthreads();
 
-  // ---- this wave's rows (level, n; wave-uniform) and rho of the own elements ----
-  int rq[NR], rn[NR];
-  cpx<T> rho[NR], z[NR];
+  // ---- rho of the own elements; slot (q, m) is row n = rs0 + wave + NW m of level q ----
+  cpx<T> rho[NS], z[NS];
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const int k = wave + NW * q;
-    rq[q] = k / h0;
-    rn[q] = k < nrow0 ? rs0 + (k - rq[q] * h0) : -1;  // -1: no row (outside every region)
-    rho[q] = mkc<T>(0, 0);
-    z[q] = mkc<T>(0, 0);
-    if (rn[q] >= 0 && act0) rho[q] = buf[PAD + (rq[q] * Wr + rn[q] - wr0) * RS + lcol];
-  }
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+      const int nr = rs0 + wave + NW * m;
+      rho[q * MM + m] = nr < rs0 + h0 ? buf[lcol + (q * WS + nr) * RS] : mkc<T>(0, 0);
+      z[q * MM + m] = mkc<T>(0, 0);
+    }
 
-  // L(Y) at row (qr, nr) (wave-uniform) and this lane's column, Y in LDS.
-  auto lval = [&](int qr, int nr) -> cpx<T> {
-    const int i = qr * N + nr;
-    const int base = PAD + (qr * Wr + nr - wr0) * RS + lcol;
-    cpx<T> acc = mkc<T>(0, 0);
-    const cpx<T> y0 = buf[base];
+  // The eight coefficients of row (q, nr) (wave-uniform: one scalar load);
+  // rows past the matrix read row 0 instead (unused).
+  auto rowcoef = [&](int q, int nr, cpx<T> (&cr)[FSLOT]) {
+    const int i = nr < N ? q * N + nr : 0;
+    const cpx<T>* __restrict__ rc = cb + i * FSLOT;
 #pragma unroll
-    for (int a = 0; a < FMAXA; ++a)
-      if (a < nA) {
-        const cpx<T> cr = cb[a * d + i];
-        const int qq = qr + g.aq[a];
-        const int dr = (qq >= 0 && qq < nq) ? g.aq[a] * QS + g.an[a] * RS : 0;
-        const cpx<T> yr = a == 0 ? y0 : buf[base + dr];
-        const cpx<T> yc = a == 0 ? y0 : buf[base + dCa[a]];
-        cfma(acc, cr, yr);
-        cfmac(acc, yc, cC[a]);
-      }
-#pragma unroll
-    for (int s = 0; s < FMAXD; ++s)
-      if (s < nD) {
-        const cpx<T> dl = ops.Dl[s * d + i];
-        const int qq = qr + g.tq[s];
-        const int dr = (qq >= 0 && qq < nq) ? g.tq[s] * QS + g.tn[s] * RS : 0;
-        const cpx<T> yd = s == 0 ? y0 : buf[base + dr + dCt[s]];
-        cfma(acc, cmulc(dl, dC[s]), yd);
-      }
+    for (int a = 0; a < FSLOT; ++a) cr[a] = rc[a];
+  };
+  // L(Y) at row (q, nr) and this lane's column, Y in LDS: the taps are read
+  // first (compile-time offsets from one address), then combined; the three
+  // taps on the element itself (A Y, Y A^dag and the (0, 0) dissipator)
+  // share one coefficient.
+  auto lval = [&](auto qi, int nr, const cpx<T> (&cr)[FSLOT]) -> cpx<T> {
+    constexpr int q = decltype(qi)::value;
+    const cpx<T>* __restrict__ bp = buf + (lcol + (q * WS + nr) * RS - LOW);
+    const cpx<T> y0 = bp[LOW];
+    const cpx<T> yrp = bp[LOW + RS], yrm = bp[LOW - RS];
+    const cpx<T> ycp = bp[LOW + NQ], ycm = bp[LOW - NQ];
+    const cpx<T> yd1 = bp[LOW + S * (RS + NQ)];
+    cpx<T> yqm, yqp, ycqm, ycqp, yd2;
+    if constexpr (NQ > 1) {
+      // diagonals -N, +N (the row shift is dropped at the first / last level,
+      // where the coefficient is zero)
+      yqm = bp[LOW - (q > 0 ? QS : 0)];
+      yqp = bp[LOW + (q < NQ - 1 ? QS : 0)];
+      ycqm = bp[LOW - 1];
+      ycqp = bp[LOW + 1];
+      constexpr int dq = (q + S >= 0 && q + S < NQ) ? S * QS : 0;
+      yd2 = bp[LOW + dq + S];
+    }
+    cpx<T> c00 = cmulc(cr[5], dC[0]);
+    c00.re += cr[0].re + cC[0].re;
+    c00.im += cr[0].im - cC[0].im;
+    cpx<T> acc = mkc<T>(fmad(c00.re, y0.re, -(c00.im * y0.im)), fmad(c00.re, y0.im, c00.im * y0.re));
+    cfma(acc, cr[1], yrp);
+    cfmac(acc, ycp, cC[1]);
+    cfma(acc, cr[2], yrm);
+    cfmac(acc, ycm, cC[2]);
+    if constexpr (NQ > 1) {
+      cfma(acc, cr[3], yqm);
+      cfmac(acc, ycqm, cC[3]);
+      cfma(acc, cr[4], yqp);
+      cfmac(acc, ycqp, cC[4]);
+    }
+    cfma(acc, cmulc(cr[6], dC[1]), yd1);
+    if constexpr (NQ > 1) cfma(acc, cmulc(cr[7], dC[2]), yd2);
     return acc;
   };
 
@@ -866,39 +970,59 @@ __device__ __forceinline__ void rk4_fused_body(const BandOps<T>& ops, const Fuse
     const int hs = 3 - s;
     const int rlo = max(r0 - hs, 0), rhi = min(r1 + hs, N);
     const bool lact = act0 && n_c >= max(c0 - hs, 0) && n_c < min(c1 + hs, N);
+    cpx<T> crn[FSLOT];
+    rowcoef(0, rs0 + wave, crn);
+    static_for<NQ>([&](auto qi) {
+      constexpr int q = decltype(qi)::value;
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const int qr = rq[q], nr = rn[q];
-      if (nr >= rlo && nr < rhi && lact) {
-        const cpx<T> v = lval(qr, nr);
-        z[q] = mkc<T>(fmad(cs, v.re, rho[q].re), fmad(cs, v.im, rho[q].im));
+      for (int m = 0; m < MM; ++m) {
+        const int nr = rs0 + wave + NW * m;
+        cpx<T> cr[FSLOT];
+#pragma unroll
+        for (int a = 0; a < FSLOT; ++a) cr[a] = crn[a];
+        // the next slot's coefficients, fetched while this row is computed
+        if (m + 1 < MM)
+          rowcoef(q, nr + NW, crn);
+        else if (q + 1 < NQ)
+          rowcoef(q + 1, rs0 + wave, crn);
+        if (nr >= rlo && nr < rhi) {
+          const cpx<T> v = lval(qi, nr, cr);
+          const cpx<T> r = rho[q * MM + m];
+          z[q * MM + m] = mkc<T>(fmad(cs, v.re, r.re), fmad(cs, v.im, r.im));
+        }
       }
-    }
+    });
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const int qr = rq[q], nr = rn[q];
-      if (nr >= rlo && nr < rhi && lact) buf[PAD + (qr * Wr + nr - wr0) * RS + lcol] = z[q];
-    }
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int m = 0; m < MM; ++m) {
+        const int nr = rs0 + wave + NW * m;
+        if (nr >= rlo && nr < rhi) buf[lact ? lcol + (q * WS + nr) * RS : scratch] = z[q * MM + m];
+      }
     __syncthreads();
   }
 
   // ---- final stage on the tile: rho' = rho + h L(Z3), compensated in float32 ----
   const bool lact = act0 && n_c >= c0 && n_c < c1;
   const bool comp = P.slo != nullptr;
-  cpx<T> zl[NR];
+  cpx<T> zl[NS];
   bool bad = false;
+  static_for<NQ>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    zl[q] = mkc<T>(0, 0);
-    {
-      const int qr = rq[q], nr = rn[q];
-      if (nr >= r0 && nr < r1 && lact) {
-        const cpx<T> v = lval(qr, nr);
-        const bool canon = !dtile || nr < n_c || (nr == n_c && qr <= qc);
-        const int i = qr * N + nr;
+    for (int m = 0; m < MM; ++m) {
+      const int sl = q * MM + m;
+      zl[sl] = mkc<T>(0, 0);
+      const int nr = rs0 + wave + NW * m;
+      if (nr >= r0 && nr < r1) {
+        cpx<T> cr[FSLOT];
+        rowcoef(q, nr, cr);
+        const cpx<T> v = lval(qi, nr, cr);
+        const int i = q * N + nr;
         const long e = (long)i * d + jcol;
-        cpx<T> hi = rho[q], lo = mkc<T>(0, 0);
+        const bool canon = lact && (!dtile || nr < n_c || (nr == n_c && q <= qc));
+        cpx<T> hi = rho[sl], lo = mkc<T>(0, 0);
         const cpx<T> dl = cscale(h, v);
         if (comp) {
           if (canon) lo = lo_at(P.slo, d, e);
@@ -911,8 +1035,8 @@ __device__ __forceinline__ void rk4_fused_body(const BandOps<T>& ops, const Fuse
           hi.im = 0;
           lo.im = 0;
         }
-        z[q] = hi;
-        zl[q] = lo;
+        z[sl] = hi;
+        zl[sl] = lo;
         if (canon) {
           bad |= !(isfinite(hi.re) && isfinite(hi.im));
           P.ohi[e] = hi;
@@ -920,36 +1044,37 @@ __device__ __forceinline__ void rk4_fused_body(const BandOps<T>& ops, const Fuse
         }
       }
     }
-  }
+  });
   if (bad) *status = 1;
   // ---- conjugate mirror (j, i) of the canonical elements, through LDS ----
   const int Tr = r1 - r0, Tc = c1 - c0;
-  const int nst = nq * nq * Tr * Tc;
+  const int SP = fused_stage_stride(NQ, Tr);  // staging stride per column (q_c, n_c)
+  const int nst = NQ * Tc * SP;
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    {
-      const int qr = rq[q], nr = rn[q];
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+      const int nr = rs0 + wave + NW * m;
       if (nr >= r0 && nr < r1 && lact) {
-        // transposed staging: [q_c][n_c][q_r][n_r]
-        const int si = ((qc * Tc + n_c - c0) * nq + qr) * Tr + (nr - r0);
-        buf[si] = z[q];
-        if (comp) buf[nst + si] = zl[q];
+        // transposed staging: column (q_c, n_c), then row (q_r, n_r)
+        const int si = (qc * Tc + n_c - c0) * SP + q * Tr + (nr - r0);
+        buf[si] = z[q * MM + m];
+        if (comp) buf[nst + si] = zl[q * MM + m];
       }
     }
-  }
   __syncthreads();
-  if (lane < nq * Tr) {
+  if (lane < NQ * Tr) {
     const int qr = lane / Tr;
     const int nr = r0 + (lane - qr * Tr);
     const int i = qr * N + nr;
-    for (int kk = wave; kk < nq * Tc; kk += NW) {
+    for (int kk = wave; kk < NQ * Tc; kk += NW) {
       const int qcc = kk / Tc;
       const int ncc = c0 + (kk - qcc * Tc);
       const int j = qcc * N + ncc;
       const bool canon = !dtile || nr < ncc || (nr == ncc && qr <= qcc);
       if (canon && i != j) {
-        const int si = kk * nq * Tr + lane;
+        const int si = kk * SP + lane;
         const long e = (long)j * d + i;
         P.ohi[e] = conjg(buf[si]);
         if (comp) lo_st(P.olo, e, conjg(buf[nst + si]));
@@ -959,15 +1084,18 @@ __device__ __forceinline__ void rk4_fused_body(const BandOps<T>& ops, const Fuse
 }
 
 // Batched launch: grid.x = B * ntile (the tiles of one problem on one XCD),
-// NW * 64 threads, dynamic LDS of fused_lds_elems(...) elements.
-template <typename T, int NW>
-__global__ __launch_bounds__(NW * 64) void rk4_fused_kernel(BandOps<T> ops, FusedGeo g, StageIO<T> io, int d,
-                                                            const cpx<T>* __restrict__ coef, T h) {
+// NW * 64 threads, dynamic LDS of fused_lds_elems(...) elements.  coef holds
+// the problems' rows of FSLOT coefficients (fused_coef_kernel), drt the
+// column factors of the dissipator taps (d x FDR).
+template <typename T, int NQ, int NW, int S>
+__global__ __launch_bounds__(NW * 64) void rk4_fused_kernel(FusedGeo g, StageIO<T> io, int d,
+                                                            const cpx<T>* __restrict__ coef,
+                                                            const cpx<T>* __restrict__ drt, T h) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(fused_smem);
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int b = L / g.ntile, t = L - b * g.ntile;
-  rk4_fused_body<T, NW>(ops, g, resolve_strided(io, b), coef + (long)b * ops.nA * d, h, io.status, t, d, buf);
+  rk4_fused_body<T, NQ, NW, S>(g, resolve_strided(io, b), coef + (long)b * FSLOT * d, drt, h, io.status, t, d, buf);
 }
 
 // Slot-table launch (continuous batching): request b of the launch reads
@@ -980,16 +1108,17 @@ struct FusedSlot {
   const cpx<T>* s_lo;
   cpx<T>* o_hi;
   cpx<T>* o_lo;
-  const cpx<T>* coef;  // diagonal coefficients of this request's slice
+  const cpx<T>* coef;  // this request's rows of FSLOT coefficients for its slice
 };
 template <typename T>
 struct FusedSlotTable {
   FusedSlot<T> e[MAXFSLOT];
 };
 
-template <typename T, int NW>
-__global__ __launch_bounds__(NW * 64) void rk4_fused_slots_kernel(BandOps<T> ops, FusedGeo g,
-                                                                  FusedSlotTable<T> tab, T h, int* status, int d) {
+template <typename T, int NQ, int NW, int S>
+__global__ __launch_bounds__(NW * 64) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
+                                                                  const cpx<T>* __restrict__ drt, T h,
+                                                                  int* status, int d) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(fused_smem);
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -1002,7 +1131,41 @@ __global__ __launch_bounds__(NW * 64) void rk4_fused_slots_kernel(BandOps<T> ops
   P.ohi = s.o_hi;
   P.olo = s.o_lo;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  rk4_fused_body<T, NW>(ops, g, P, s.coef, h, status, t, d, buf);
+  rk4_fused_body<T, NQ, NW, S>(g, P, s.coef, drt, h, status, t, d, buf);
+}
+
+// Coefficients of the fused step for the slots of a serving launch:
+// request b of the launch (gridDim.y) at its own slice row urow.
+template <typename T>
+struct FusedCoefSlots {
+  cpx<T>* coef[MAXFSLOT];
+  const double* urow[MAXFSLOT];
+};
+template <typename T>
+__global__ __launch_bounds__(256) void fused_coef_slots_kernel(const cpx<T>* __restrict__ a0,
+                                                               const cpx<T>* __restrict__ ak,
+                                                               const cpx<T>* __restrict__ dl, int d, int K,
+                                                               FusedCoefSlots<T> tab) {
+  const int b = blockIdx.y;
+  const double* ub = tab.urow[b];
+  cpx<T>* out = tab.coef[b];
+  const int n = FSLOT * d;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const int i = e / FSLOT, a = e - i * FSLOT;
+    cpx<T> v;
+    if (a < 5) {
+      v = a0[i * 5 + a];
+      for (int k = 0; k < K; ++k) {
+        const T uk = (T)ub[k];
+        const cpx<T> hh = ak[((long)k * d + i) * 5 + a];
+        v.re += uk * hh.re;
+        v.im += uk * hh.im;
+      }
+    } else {
+      v = dl[i * 3 + (a - 5)];
+    }
+    out[e] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
