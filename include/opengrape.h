@@ -189,8 +189,9 @@ og_status og_set_resident(og_ctx *ctx, int n_slices);
  * have the structure of a multi-level system coupled to an oscillator
  * (Sec. IV): d = nq N, index q N + n, diagonals of the generator at offsets
  * 0, +-1 (no coupling between blocks of N) and +-N, dissipator taps
- * (0, 0), (+-1, +-1) and (+-N, +-N), with nq (T + 6) <= 64 for some tile
- * edge T >= 2 -- every fixed RK4 step of the forward sweep, its recompute
+ * (0, 0), (s, s) and (s N, s N) with one sign s = +-1 and real factors
+ * gamma c[i, i + p], nq <= 4 and nq (T + 6) <= 64 for a tile edge T >= 2 --
+ * every fixed RK4 step of the forward sweep, its recompute
  * and the first-order adjoint sweep runs as one kernel that keeps a tile of
  * the state with a halo of four in on-chip memory through the four nested
  * stages, instead of four stage kernels that each read and write the whole

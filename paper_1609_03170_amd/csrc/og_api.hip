@@ -430,7 +430,8 @@ struct Engine : EngineBase {
   // Structure test of the fused RK4 step (rk4_fused_kernel) for direction
   // s of the operators h, on the dissipator taps (tp, tq, values dl, dr) of
   // the banded setup: diagonals of A(u) only at 0, +-1 and +-N with
-  // d = nq N, taps (0, 0), (s, s) with s = +-1 and (t N, t N) with t = +-1;
+  // d = nq N, taps (0, 0), (s, s) with s = +-1 and (t N, t N) with t = +-1
+  // of one sign, with real factors;
   // the +-1 couplings must vanish between blocks of N (rows n = N - 1 for +1,
   // n = 0 for -1); nq <= 4 and a tile edge T with nq (T + 6) <= 64 whose LDS
   // needs fit in 64 KiB.  Then the coefficient data of the fused step are
@@ -471,6 +472,10 @@ struct Engine : EngineBase {
     if (N < 2 || d % N != 0) return OG_OK;
     const int nq = d / N;
     if (nq > 4 || (nq == 1 && i2 >= 0)) return OG_OK;
+    for (int t : {i0, i1, i2})  // the kernel takes the dissipator factors as real
+      if (t >= 0)
+        for (int i = 0; i < d; ++i)
+          if (dl[t][i].imag() != 0.0 || dr[t][i].imag() != 0.0) return OG_OK;
     if (s1 == 0) s1 = t2 != 0 ? t2 : 1;  // no (+-1, +-1) tap: a zero one
     if (t2 != 0 && t2 != s1) return OG_OK;  // compiled for taps (s, s), (s N, s N) of one sign
     if (t2 == 0 && nq > 1) t2 = s1;         // no (t N, t N) tap: a zero one

@@ -707,7 +707,8 @@ __global__ __launch_bounds__(TS * TS / SlotCfg<T>::NQ) void band_stage_slots_ker
 // (the transmon x resonator models of Sec. IV): d = NQ N, index i = q N + n;
 // A(u) has diagonals at offsets 0, +1, -1 (never linking one block of N to
 // the next), -N, +N; the dissipator taps are (0, 0), (s, s) with s = +-1 and
-// (t N, t N) with t = +-1.  One stage of L then reaches one step in n and one
+// (t N, t N) with t = +-1, with real factors gamma C[i, i + p] and C[j, j + p]
+// (the real matrix elements of ladder and number operators).  One stage of L then reaches one step in n and one
 // step in q.  A block computes the step on one tile of n-ranges
 // [r0, r1) x [c0, c1) for all NQ x NQ level pairs, so the q-couplings stay
 // inside the tile and the n-halo grows by one per stage: the tile and a halo
@@ -895,11 +896,12 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
   const int n_c = cs0 + cn0;
   const int jcol = qc * N + n_c;
   const int lcol = PAD + (n_c - wc0) * NQ + qc - wr0 * RS;  // + (q WS + n_r) RS: the element's LDS index
-  cpx<T> cC[5], dC[3];
+  cpx<T> cC[5];
+  T dC[3];  // the dissipator column factors are real (checked on the host)
 #pragma unroll
   for (int a = 0; a < 5; ++a) cC[a] = cb[jcol * FSLOT + a];
 #pragma unroll
-  for (int s = 0; s < 3; ++s) dC[s] = drt[jcol * FDR + s];
+  for (int s = 0; s < 3; ++s) dC[s] = drt[jcol * FDR + s].re;
 
   __syncthreads();
 
@@ -944,9 +946,8 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
       constexpr int dq = (q + S >= 0 && q + S < NQ) ? S * QS : 0;
       yd2 = bp[LOW + dq + S];
     }
-    cpx<T> c00 = cmulc(cr[5], dC[0]);
-    c00.re += cr[0].re + cC[0].re;
-    c00.im += cr[0].im - cC[0].im;
+    // dissipator taps: real row factor (slots 5..7, real part) times real column factor
+    const cpx<T> c00 = mkc<T>(fmad(cr[5].re, dC[0], cr[0].re + cC[0].re), cr[0].im - cC[0].im);
     cpx<T> acc = mkc<T>(fmad(c00.re, y0.re, -(c00.im * y0.im)), fmad(c00.re, y0.im, c00.im * y0.re));
     cfma(acc, cr[1], yrp);
     cfmac(acc, ycp, cC[1]);
@@ -958,8 +959,14 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
       cfma(acc, cr[4], yqp);
       cfmac(acc, ycqp, cC[4]);
     }
-    cfma(acc, cmulc(cr[6], dC[1]), yd1);
-    if constexpr (NQ > 1) cfma(acc, cmulc(cr[7], dC[2]), yd2);
+    const T f1 = cr[6].re * dC[1];
+    acc.re = fmad(f1, yd1.re, acc.re);
+    acc.im = fmad(f1, yd1.im, acc.im);
+    if constexpr (NQ > 1) {
+      const T f2 = cr[7].re * dC[2];
+      acc.re = fmad(f2, yd2.re, acc.re);
+      acc.im = fmad(f2, yd2.im, acc.im);
+    }
     return acc;
   };
 
@@ -970,22 +977,14 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
     const int hs = 3 - s;
     const int rlo = max(r0 - hs, 0), rhi = min(r1 + hs, N);
     const bool lact = act0 && n_c >= max(c0 - hs, 0) && n_c < min(c1 + hs, N);
-    cpx<T> crn[FSLOT];
-    rowcoef(0, rs0 + wave, crn);
     static_for<NQ>([&](auto qi) {
       constexpr int q = decltype(qi)::value;
 #pragma unroll
       for (int m = 0; m < MM; ++m) {
         const int nr = rs0 + wave + NW * m;
-        cpx<T> cr[FSLOT];
-#pragma unroll
-        for (int a = 0; a < FSLOT; ++a) cr[a] = crn[a];
-        // the next slot's coefficients, fetched while this row is computed
-        if (m + 1 < MM)
-          rowcoef(q, nr + NW, crn);
-        else if (q + 1 < NQ)
-          rowcoef(q + 1, rs0 + wave, crn);
         if (nr >= rlo && nr < rhi) {
+          cpx<T> cr[FSLOT];
+          rowcoef(q, nr, cr);
           const cpx<T> v = lval(qi, nr, cr);
           const cpx<T> r = rho[q * MM + m];
           z[q * MM + m] = mkc<T>(fmad(cs, v.re, r.re), fmad(cs, v.im, r.im));
@@ -1088,7 +1087,7 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
 // the problems' rows of FSLOT coefficients (fused_coef_kernel), drt the
 // column factors of the dissipator taps (d x FDR).
 template <typename T, int NQ, int NW, int S>
-__global__ __launch_bounds__(NW * 64) void rk4_fused_kernel(FusedGeo g, StageIO<T> io, int d,
+__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 4 : 2) void rk4_fused_kernel(FusedGeo g, StageIO<T> io, int d,
                                                             const cpx<T>* __restrict__ coef,
                                                             const cpx<T>* __restrict__ drt, T h) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
@@ -1116,7 +1115,7 @@ struct FusedSlotTable {
 };
 
 template <typename T, int NQ, int NW, int S>
-__global__ __launch_bounds__(NW * 64) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
+__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 4 : 2) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
                                                                   const cpx<T>* __restrict__ drt, T h,
                                                                   int* status, int d) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
