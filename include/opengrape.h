@@ -286,6 +286,30 @@ og_status og_adjoint(og_ctx *ctx, const void *sigma, void *stream);
 og_status og_gradient(og_ctx *ctx, double *grad, void *stream);
 
 /*
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: one whole
+ * evaluation (og_forward, og_cost, og_adjoint, og_gradient in that order,
+ * same arguments and results: phi device float64 B, grad device float64
+ * B x n_t x K) whose workspace is a buffer of the library instead of the
+ * caller's: a device array of OG_STATIC_WS_BYTES (256 MiB) per GPU, created
+ * with the library's code on every GPU it runs on and held until the
+ * process ends (its address is resolved at og_create).  Allocates nothing
+ * and never synchronizes: no stability check and no read-back of the
+ * non-finite flag, whatever the context's validate option (check phi and
+ * grad instead).  Returns OG_ERR_WORKSPACE, with nothing enqueued, when
+ * og_workspace_bytes(ctx, B, n_t) exceeds OG_STATIC_WS_BYTES, and OG_ERR_ARG
+ * with adaptive steps on (they read every attempt back).  Every call on one
+ * GPU shares that GPU's buffer, which keeps the last call's contents: calls
+ * in stream order are safe, calls that overlap on one GPU (two streams, two
+ * host threads) race.  Afterwards the context is in the state of a finished
+ * og_gradient (og_cost / og_gradient may be called again; the workspace is
+ * the shared buffer, so only until the next og_evaluate_static).
+ */
+#define OG_STATIC_WS_BYTES (256u << 20)
+og_status og_evaluate_static(og_ctx *ctx, int B, int n_t, double dt, const double *u, const void *rho0,
+                             const void *sigma, double *phi, double *grad, void *stream);
+
+/*
  * Multi-state index (Eq. (22), Sec. IV.B): with the B problems of the batch
  * being the input states rho_i(0) of one control array (u repeated for every
  * b), Phi = sum_i Tr(sigma rho_i(T)) and its gradient is the sum over the

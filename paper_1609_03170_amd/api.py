@@ -40,8 +40,9 @@ EXPORTS = (
     "og_server_create", "og_server_submit", "og_server_step", "og_server_active", "og_server_completed",
     "og_server_destroy", "og_status_string", "og_last_error", "og_gradient_sum", "og_set_penalty",
     "og_filter_apply", "og_filter_grad", "og_create_banded", "og_set_adaptive", "og_adaptive_stats",
-    "og_set_resident", "og_generation", "og_set_fused", "og_fused_used",
+    "og_set_resident", "og_generation", "og_set_fused", "og_fused_used", "og_evaluate_static",
 )
+STATIC_WS_BYTES = 256 << 20  # OG_STATIC_WS_BYTES
 
 
 class OgRequest(ctypes.Structure):
@@ -108,6 +109,8 @@ def load_library(path: str = LIB_PATH):
     lib.og_adaptive_stats.restype = i
     lib.og_set_resident.argtypes = [vp, i]
     lib.og_set_resident.restype = i
+    lib.og_evaluate_static.argtypes = [vp, i, i, d, vp, vp, vp, vp, vp, vp]
+    lib.og_evaluate_static.restype = i
     lib.og_set_fused.argtypes = [vp, i]
     lib.og_set_fused.restype = i
     lib.og_fused_used.argtypes = [vp]
@@ -338,6 +341,24 @@ class Problem:
         phi = self.cost(sigma)
         self.adjoint(sigma)
         return phi, self.gradient()
+
+    def evaluate_static(self, u, rho0, sigma, dt):
+        """Phi[b] and dPhi/du[b] like cost_and_grad, with the library's static
+        workspace (og_evaluate_static: no device allocation by the library,
+        no synchronisation).  The output tensors are allocated here by torch;
+        callers that cannot allocate call the C ABI with their own buffers."""
+        u = self._as_u(u)
+        B, n_t = u.shape[0], u.shape[1]
+        rho0 = self._as_states(rho0, B)
+        sigma = self._as_states(sigma, 1)[0].contiguous()
+        phi = torch.empty(B, dtype=torch.float64, device=self.device)
+        g = torch.empty((B, n_t, self.K), dtype=torch.float64, device=self.device)
+        self._keep = dict(u=u, rho0=rho0, sigma=sigma, B=B, n_t=n_t)
+        with torch.cuda.device(self.device):
+            _check(self._lib.og_evaluate_static(self._ctx, B, n_t, float(dt), u.data_ptr(), rho0.data_ptr(),
+                                                sigma.data_ptr(), phi.data_ptr(), g.data_ptr(),
+                                                _stream_ptr(self.device)))
+        return phi, g
 
     def gradient_sum(self, out=None):
         """sum_b dPhi_b/du (multi-state index, Eq. (22)); adds into `out` if given."""

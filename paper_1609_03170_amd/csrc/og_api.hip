@@ -23,6 +23,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -211,6 +212,31 @@ std::vector<cd> concat(const std::vector<std::vector<cd>>& parts) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int kUmaxBlocks = 64;  // blocks of the max|u| reduction
+
+// Workspace of og_evaluate_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never uses its name as an
+// address (that is a host-side stand-in); the device address of each GPU's
+// copy is resolved once per device with hipGetSymbolAddress (at og_create,
+// or at the first og_evaluate_static on a device) and kept in
+// g_scratch_ptr.
+constexpr size_t kStaticWsBytes = size_t(OG_STATIC_WS_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (nullptr on error).
+void* scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 // ---------------------------------------------------------------------------
 // Operator data of one direction of propagation
@@ -1931,6 +1957,10 @@ og_status og_create(og_ctx** out, int d, int K, int J, const void* H0p, const vo
     og_destroy(ctx);
     return fail(OG_ERR_DEVICE, "hipMemset failed");
   }
+  if (!scratch_ptr()) {  // og_evaluate_static's workspace on this device, resolved once
+    og_destroy(ctx);
+    return fail(OG_ERR_DEVICE, "hipGetSymbolAddress of the static workspace failed");
+  }
   og_status s;
   if (opt.prec == OG_F64) {
     auto* e = new Engine<double>(ctx);
@@ -2162,6 +2192,48 @@ og_status og_gradient_sum(og_ctx* ctx, double* grad, int accumulate, void* strea
     if (flag) return fail(OG_ERR_NONFINITE, "a propagated state became non-finite");
   }
   return OG_OK;
+}
+
+og_status og_evaluate_static(og_ctx* ctx, int B, int n_t, double dt, const double* u, const void* rho0,
+                             const void* sigma, double* phi, double* grad, void* stream) {
+  g_err.clear();
+  if (!ctx || !ctx->eng) return fail(OG_ERR_ARG, "ctx is NULL");
+  if (B < 1 || B > (1 << 20)) return fail(OG_ERR_ARG, "B must be >= 1");
+  if (n_t < 1) return fail(OG_ERR_ARG, "n_t must be >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(OG_ERR_ARG, "dt must be finite and > 0");
+  if ((ctx->K > 0 && (!u || !grad)) || !rho0 || !sigma || !phi) return fail(OG_ERR_ARG, "NULL argument");
+  if (ctx->ad_rtol > 0.0)
+    return fail(OG_ERR_ARG, "adaptive steps read every attempt back to the host; og_evaluate_static runs fixed steps");
+  const size_t need = ctx->eng->ws_bytes(B, n_t);
+  if (need > kStaticWsBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "evaluation needs %zu bytes of workspace; the static workspace holds %zu", need,
+             kStaticWsBytes);
+    return fail(OG_ERR_WORKSPACE, buf);
+  }
+  void* ws = scratch_ptr();
+  if (!ws) return fail(OG_ERR_DEVICE, "hipGetSymbolAddress of the static workspace failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // no event sampling here (it creates events)
+  const int prof = ctx->prof_every;
+  ctx->prof_every = 0;
+  ctx->phase = 0;
+  og::clear_status_kernel<<<1, 64, 0, st>>>(ctx->status_dev);
+  og_status s = OG_OK;
+  if (hipGetLastError() != hipSuccess) s = fail(OG_ERR_DEVICE, "kernel launch failed");
+  if (s == OG_OK) s = ctx->eng->forward(B, n_t, dt, u, rho0, nullptr, ws, need, st);
+  if (s == OG_OK) {
+    ctx->phase = 1;
+    ++ctx->generation;
+    s = ctx->eng->cost(sigma, phi, st);
+  }
+  if (s == OG_OK) s = ctx->eng->adjoint(sigma, st);
+  if (s == OG_OK) {
+    ctx->phase = 2;
+    s = ctx->eng->gradient(grad, st);
+  }
+  ctx->prof_every = prof;
+  return s;
 }
 
 og_status og_set_penalty(og_ctx* ctx, const void* A, double beta) {

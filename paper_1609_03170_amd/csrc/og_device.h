@@ -1934,6 +1934,11 @@ __global__ __launch_bounds__(256) void store_state_kernel(const cpx<T>* __restri
   }
 }
 
+// status = 0 (a kernel, not a memset node, for callers under graph capture)
+__global__ __launch_bounds__(64) void clear_status_kernel(int* __restrict__ status) {
+  if (threadIdx.x == 0) status[0] = 0;
+}
+
 // Partial maxima max |u[r, k]| over the rows r = blockIdx.x, blockIdx.x +
 // gridDim.x, ... for every k: out[blockIdx.x * K + k].  A NaN propagates.
 __global__ __launch_bounds__(256) void umax_kernel(const double* __restrict__ u, long n_rows, int K,

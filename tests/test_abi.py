@@ -86,6 +86,7 @@ def test_host_argument_errors_without_gpu():
     assert lib.og_generation(None) == 0
     assert lib.og_set_fused(None, 1) == -1
     assert lib.og_fused_used(None) == 0
+    assert lib.og_evaluate_static(None, 1, 1, 0.1, None, None, None, None, None, None) == -1
 
 
 def test_create_banded_argument_errors_without_gpu():
