@@ -288,7 +288,12 @@ class Problem:
         rho0 = self._as_states(rho0, B)
         need = self.workspace_bytes(B, n_t)
         if workspace is None or workspace.numel() < need:
-            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+            old = self._keep.get("ws")
+            if old is not None and old.numel() >= need:
+                workspace = old  # the previous evaluation's workspace, reused
+            else:
+                self._keep = {}  # release it before allocating a larger one
+                workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
         rhoT = torch.empty((B, self.d, self.d), dtype=torch.complex128, device=self.device) if want_rho_T else None
         self._keep = dict(u=u, rho0=rho0, ws=workspace, B=B, n_t=n_t)
         with torch.cuda.device(self.device):
