@@ -364,6 +364,7 @@ struct Engine : EngineBase {
   bool fused[2] = {false, false};
   og::FusedGeo fgeo[2]{};
   size_t fused_lds[2] = {0, 0};
+  size_t fused_lds_slots[2] = {0, 0};  // serving launches: + the coefficient rows of the window
   static constexpr int kFusedNW = sizeof(T) == 4 ? 4 : 8;  // waves per block
   // fused-step coefficient data per direction: A0 and A_k on the five
   // diagonals (0, +1, -1, -N, +N) row by row (d x 5, K x d x 5), the row
@@ -526,9 +527,11 @@ struct Engine : EngineBase {
     const int tlane = 64 / nq - 6;
     int nb = (N + tlane - 1) / tlane;
     size_t bytes = 0;
+    size_t bytes_lc = 0;
     for (; nb <= N; ++nb) {
       const int tmax = (N + nb - 1) / nb;
       bytes = (size_t)og::fused_lds_elems(nq, ws, tmax) * sizeof(og::cpx<T>);
+      bytes_lc = (size_t)og::fused_lds_elems(nq, ws, tmax, true) * sizeof(og::cpx<T>);
       if (std::min(tmax + 8, N) <= ws && bytes <= 65536) break;
     }
     if (nb > N || (N + nb - 1) / nb < 2) return OG_OK;
@@ -564,6 +567,7 @@ struct Engine : EngineBase {
     g.s1 = s1;
     g.t2 = t2;
     fused_lds[s] = bytes;
+    fused_lds_slots[s] = bytes_lc;
     fused[s] = true;
     return OG_OK;
   }
@@ -924,6 +928,16 @@ struct Engine : EngineBase {
   }
 
   bool use_fused(int dr) const { return banded && fused[dr] && ctx->fused_on; }
+  // serving launches form the coefficients in LDS as well: fused only if that still fits
+  bool use_fused_slots(int dr) const { return use_fused(dr) && fused_lds_slots[dr] <= 65536; }
+  og::FusedOps<T> fops(int dr) const {
+    og::FusedOps<T> f;
+    f.a0 = fa0[dr];
+    f.ak = fak[dr];
+    f.dl = fdl[dr];
+    f.K = K;
+    return f;
+  }
 
   // Call f(levels, sign) with the compile-time level count (1..4) and tap
   // sign (+-1) of direction dr's fused step.
@@ -983,7 +997,7 @@ struct Engine : EngineBase {
     const int n = og::FSLOT * d;
     const unsigned gx = (unsigned)std::max(1, std::min((n + 255) / 256, 64));
     og::fused_coef_kernel<T><<<dim3(gx, (unsigned)B, (unsigned)(c1 - c0)), 256, 0, st>>>(
-        fa0[dr], fak[dr], fdl[dr], d, K, u, (long)n_t * K, c0, fcoef[dr]);
+        fops(dr), d, u, (long)n_t * K, c0, fcoef[dr]);
     OG_CHECK_LAUNCH();
     fc0[dr] = c0;
     fc1[dr] = c1;
@@ -1595,17 +1609,8 @@ struct Engine : EngineBase {
           og::band_contract_slots_kernel<T, og::MAXH><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
         OG_CHECK_LAUNCH();
       }
-      if (use_fused(dr)) {
-        og::FusedCoefSlots<T> ct{};
-        for (int q = 0; q < m; ++q) {
-          const Op& o = ops[i0 + q0 + q];
-          const Slot& sl = slots[o.slot];
-          ct.coef[q] = dr == FWD ? sl.coefF : sl.coefA;
-          ct.urow[q] = sl.r.u + (long)o.slice * K;
-        }
-        const int na = og::FSLOT * d;
-        const unsigned gx = (unsigned)std::max(1, std::min((na + 255) / 256, 64));
-        og::fused_coef_slots_kernel<T><<<dim3(gx, (unsigned)m), 256, 0, st>>>(fa0[dr], fak[dr], fdl[dr], d, K, ct);
+      if (use_fused_slots(dr)) {
+        // the fused serving kernel forms its coefficients itself
       } else {
         og::SlotTable<T> ct{};
         for (int q = 0; q < m; ++q) {
@@ -1622,7 +1627,7 @@ struct Engine : EngineBase {
     }
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dtv / nsub);
-    if (use_fused(dr)) {
+    if (use_fused_slots(dr)) {
       // In-place operations (the forward state, lambda) write the request's
       // other buffer (za for the state, zb for lambda) and swap the two;
       // the segment recompute (sg[jj] -> sg[jj + 1]) chains several substeps
@@ -1634,7 +1639,7 @@ struct Engine : EngineBase {
           const Op& o = ops[i0 + q];
           Slot& sl = slots[o.slot];
           og::FusedSlot<T>& e = ft.e[q];
-          e.coef = dr == FWD ? sl.coefF : sl.coefA;
+          e.urow = sl.r.u + (long)o.slice * K;
           if (o.ihi == o.ohi) {
             og::cpx<T>*& cur = dr == FWD ? sl.cur_hi : sl.lam_hi;
             og::cpx<T>*& alt = dr == FWD ? sl.za : sl.zb;
@@ -1654,7 +1659,8 @@ struct Engine : EngineBase {
         const long pidx = ctx->prof_begin(st);
         fused_dispatch(dr, [&](auto nq, auto sg) {
           og::rk4_fused_slots_kernel<T, decltype(nq)::value, kFusedNW, decltype(sg)::value>
-              <<<grid, kFusedNW * 64, fused_lds[dr], st>>>(fgeo[dr], ft, fdr[dr], h, ctx->status_dev, d);
+              <<<grid, kFusedNW * 64, fused_lds_slots[dr], st>>>(fgeo[dr], ft, fops(dr), fdr[dr], h,
+                                                                 ctx->status_dev, d);
         });
         OG_CHECK_LAUNCH();
         ctx->prof_end(pidx, st);
@@ -1694,7 +1700,7 @@ struct Engine : EngineBase {
     // (MAXFSLOT with the fused step)
     std::stable_sort(ops.begin(), ops.end(),
                      [&](const Op& a, const Op& b) { return slots[a.slot].r.dt < slots[b.slot].r.dt; });
-    const size_t cap = use_fused(dr) ? (size_t)og::MAXFSLOT : (size_t)og::MAXSLOT;
+    const size_t cap = use_fused_slots(dr) ? (size_t)og::MAXFSLOT : (size_t)og::MAXSLOT;
     size_t i = 0;
     while (i < ops.size()) {
       const double dtv = slots[ops[i].slot].r.dt;

@@ -767,29 +767,20 @@ __device__ __forceinline__ int2 fused_tile(int t, int nb) {
 // A(u_j) = A0 + sum_k u[b, j, k] Ak at row i (slots 0..4) and the row
 // factors of the dissipator taps (slots 5..7, constant).
 template <typename T>
-__global__ __launch_bounds__(256) void fused_coef_kernel(const cpx<T>* __restrict__ a0, const cpx<T>* __restrict__ ak,
-                                                         const cpx<T>* __restrict__ dl, int d, int K,
-                                                         const double* __restrict__ u, long u_bs, int jslice,
-                                                         cpx<T>* __restrict__ coef) {
+struct FusedOps;
+template <typename T>
+__device__ __forceinline__ cpx<T> fused_coef_at(const FusedOps<T>& fo, const double* __restrict__ ub, int d, int i,
+                                                int a);
+template <typename T>
+__global__ __launch_bounds__(256) void fused_coef_kernel(FusedOps<T> fo, int d, const double* __restrict__ u,
+                                                         long u_bs, int jslice, cpx<T>* __restrict__ coef) {
   const int b = blockIdx.y, z = blockIdx.z;
-  const double* ub = u + (long)b * u_bs + (long)(jslice + z) * K;
+  const double* ub = u + (long)b * u_bs + (long)(jslice + z) * fo.K;
   cpx<T>* out = coef + ((long)z * gridDim.y + b) * FSLOT * d;
   const int n = FSLOT * d;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     const int i = e / FSLOT, a = e - i * FSLOT;
-    cpx<T> v;
-    if (a < 5) {
-      v = a0[i * 5 + a];
-      for (int k = 0; k < K; ++k) {
-        const T uk = (T)ub[k];
-        const cpx<T> h = ak[((long)k * d + i) * 5 + a];
-        v.re += uk * h.re;
-        v.im += uk * h.im;
-      }
-    } else {
-      v = dl[i * 3 + (a - 5)];
-    }
-    out[e] = v;
+    out[e] = fused_coef_at(fo, ub, d, i, a);
   }
 }
 
@@ -811,16 +802,51 @@ __host__ __device__ __forceinline__ int fused_stage_stride(int nq, int tr) { ret
 // pads (one row and one column at both ends) and 64 scratch slots, or the
 // staging of the tile's new state (hi and lo) for the transposed write, if
 // larger (tmax: the largest tile edge).
-__host__ __device__ __forceinline__ int fused_lds_elems(int nq, int ws, int tmax) {
-  const int win = nq * nq * ws * ws + 2 * (nq * ws + nq) + 64;
+__host__ __device__ __forceinline__ int fused_lds_elems(int nq, int ws, int tmax, bool lc = false) {
+  const int win = nq * nq * ws * ws + 2 * (nq * ws + nq) + 64 + (lc ? nq * ws * FSLOT : 0);
   const int stg = 2 * nq * tmax * fused_stage_stride(nq, tmax);
   return win > stg ? win : stg;
 }
 
-template <typename T, int NQ, int NW, int S>
+// Operator rows of the fused step, for coefficients formed inside the
+// kernel: A0 and A_k on the five diagonals row by row (d x 5, K x d x 5),
+// the dissipator row factors (d x 3), and the controls u[j, :] of the slice.
+template <typename T>
+struct FusedOps {
+  const cpx<T>* a0;
+  const cpx<T>* ak;
+  const cpx<T>* dl;
+  int K;
+};
+
+// Diagonal slot a (< 5) of A(u) at row i, or dissipator row factor a - 5:
+// the arithmetic of fused_coef_kernel, so both give the same bits.
+template <typename T>
+__device__ __forceinline__ cpx<T> fused_coef_at(const FusedOps<T>& fo, const double* __restrict__ ub, int d, int i,
+                                                int a) {
+  if (a >= 5) return fo.dl[i * 3 + (a - 5)];
+  cpx<T> v = fo.a0[i * 5 + a];
+  for (int k = 0; k < fo.K; ++k) {
+    const T uk = (T)ub[k];
+    const cpx<T> hh = fo.ak[((long)k * d + i) * 5 + a];
+    v.re += uk * hh.re;
+    v.im += uk * hh.im;
+  }
+  return v;
+}
+
+// With LC (the serving launches) the coefficients are formed by the block
+// itself from fo and the slice's controls ub: the rows of its window into
+// LDS (after the window and scratch), its lanes' columns into registers, so
+// a serving step needs no coefficient launch per slice.  Otherwise cb holds
+// the problem's rows of FSLOT coefficients (fused_coef_kernel), read with
+// one scalar load per row.
+template <typename T, int NQ, int NW, int S, bool LC = false>
 __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<T>& P,
                                                const cpx<T>* __restrict__ cb, const cpx<T>* __restrict__ drt,
-                                               T h, int* status, int t, int d, cpx<T>* __restrict__ buf) {
+                                               T h, int* status, int t, int d, cpx<T>* __restrict__ buf,
+                                               const FusedOps<T>& fo = FusedOps<T>{},
+                                               const double* __restrict__ ub = nullptr) {
   // LDS layout: element (q_r, n_r; q_c, n_c) of the window at
   //   PAD + (q_r WS + n_r - wr0) RS + (n_c - wc0) NQ + q_c,
   // levels of the column innermost, so the lanes of a row read and write
@@ -833,6 +859,7 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
   constexpr int MM = (WS - 2 + NW - 1) / NW;  // rows per level per wave (h0 <= T + 6 <= WS - 2)
   constexpr int NS = NQ * MM;                 // row slots per wave
   constexpr int LOW = QS + RS + NQ;           // most negative tap offset, bounded
+  constexpr int CROW = PAD + NWIN + PAD + 64;  // LC: coefficient rows of the window, after the scratch slots
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int N = g.N, nb = g.nb;
@@ -887,6 +914,14 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
       buf[e] = mkc<T>(0, 0);
       buf[PAD + NWIN + e] = mkc<T>(0, 0);
     }
+    if constexpr (LC) {
+      // the coefficient rows of the window's rows: [q WS + n - wr0][FSLOT]
+      for (int e = tid; e < NQ * Wr * FSLOT; e += 64 * NW) {
+        const int r = e / FSLOT, a = e - r * FSLOT;
+        const int q = r / Wr, nl = r - q * Wr;
+        buf[CROW + (q * WS + nl) * FSLOT + a] = fused_coef_at(fo, ub, d, q * N + wr0 + nl, a);
+      }
+    }
   }
 
   // ---- this lane's column (lanes beyond the region compute on the last one) ----
@@ -899,7 +934,7 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
   cpx<T> cC[5];
   T dC[3];  // the dissipator column factors are real (checked on the host)
 #pragma unroll
-  for (int a = 0; a < 5; ++a) cC[a] = cb[jcol * FSLOT + a];
+  for (int a = 0; a < 5; ++a) cC[a] = LC ? fused_coef_at(fo, ub, d, jcol, a) : cb[jcol * FSLOT + a];
 #pragma unroll
   for (int s = 0; s < 3; ++s) dC[s] = drt[jcol * FDR + s].re;
 
@@ -919,10 +954,16 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
   // The eight coefficients of row (q, nr) (wave-uniform: one scalar load);
   // rows past the matrix read row 0 instead (unused).
   auto rowcoef = [&](int q, int nr, cpx<T> (&cr)[FSLOT]) {
-    const int i = nr < N ? q * N + nr : 0;
-    const cpx<T>* __restrict__ rc = cb + i * FSLOT;
+    if constexpr (LC) {
+      const cpx<T>* rc = buf + CROW + (q * WS + nr - wr0) * FSLOT;  // wave-uniform: a broadcast read
 #pragma unroll
-    for (int a = 0; a < FSLOT; ++a) cr[a] = rc[a];
+      for (int a = 0; a < FSLOT; ++a) cr[a] = rc[a];
+    } else {
+      const int i = nr < N ? q * N + nr : 0;
+      const cpx<T>* __restrict__ rc = cb + i * FSLOT;
+#pragma unroll
+      for (int a = 0; a < FSLOT; ++a) cr[a] = rc[a];
+    }
   };
   // L(Y) at row (q, nr) and this lane's column, Y in LDS: the taps are read
   // first (compile-time offsets from one address), then combined; the three
@@ -1098,8 +1139,11 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 4 : 2) void rk4_fused_ker
 }
 
 // Slot-table launch (continuous batching): request b of the launch reads
-// s_hi / s_lo of its table entry and writes o_hi / o_lo.  Up to MAXFSLOT
-// requests per launch (the table travels in the kernel arguments).
+// s_hi / s_lo of its table entry and writes o_hi / o_lo, with the
+// coefficients of its slice formed in the kernel from fo and its controls.
+// Up to MAXFSLOT requests per launch (the table travels in the kernel
+// arguments).  In float32 three waves per SIMD: the coefficient rows then
+// sit in vector registers, and four would spill them.
 constexpr int MAXFSLOT = 64;
 template <typename T>
 struct FusedSlot {
@@ -1107,7 +1151,7 @@ struct FusedSlot {
   const cpx<T>* s_lo;
   cpx<T>* o_hi;
   cpx<T>* o_lo;
-  const cpx<T>* coef;  // this request's rows of FSLOT coefficients for its slice
+  const double* urow;  // this request's controls u[j, :] of its slice
 };
 template <typename T>
 struct FusedSlotTable {
@@ -1115,9 +1159,9 @@ struct FusedSlotTable {
 };
 
 template <typename T, int NQ, int NW, int S>
-__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 4 : 2) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
-                                                                  const cpx<T>* __restrict__ drt, T h,
-                                                                  int* status, int d) {
+__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 3 : 2) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
+                                                                  FusedOps<T> fo, const cpx<T>* __restrict__ drt,
+                                                                  T h, int* status, int d) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(fused_smem);
   const int L = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -1130,41 +1174,7 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 4 : 2) void rk4_fused_slo
   P.ohi = s.o_hi;
   P.olo = s.o_lo;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  rk4_fused_body<T, NQ, NW, S>(g, P, s.coef, drt, h, status, t, d, buf);
-}
-
-// Coefficients of the fused step for the slots of a serving launch:
-// request b of the launch (gridDim.y) at its own slice row urow.
-template <typename T>
-struct FusedCoefSlots {
-  cpx<T>* coef[MAXFSLOT];
-  const double* urow[MAXFSLOT];
-};
-template <typename T>
-__global__ __launch_bounds__(256) void fused_coef_slots_kernel(const cpx<T>* __restrict__ a0,
-                                                               const cpx<T>* __restrict__ ak,
-                                                               const cpx<T>* __restrict__ dl, int d, int K,
-                                                               FusedCoefSlots<T> tab) {
-  const int b = blockIdx.y;
-  const double* ub = tab.urow[b];
-  cpx<T>* out = tab.coef[b];
-  const int n = FSLOT * d;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
-    const int i = e / FSLOT, a = e - i * FSLOT;
-    cpx<T> v;
-    if (a < 5) {
-      v = a0[i * 5 + a];
-      for (int k = 0; k < K; ++k) {
-        const T uk = (T)ub[k];
-        const cpx<T> hh = ak[((long)k * d + i) * 5 + a];
-        v.re += uk * hh.re;
-        v.im += uk * hh.im;
-      }
-    } else {
-      v = dl[i * 3 + (a - 5)];
-    }
-    out[e] = v;
-  }
+  rk4_fused_body<T, NQ, NW, S, true>(g, P, nullptr, drt, h, status, t, d, buf, fo, s.urow);
 }
 
 // ---------------------------------------------------------------------------
