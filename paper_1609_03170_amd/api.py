@@ -399,16 +399,21 @@ class Problem:
         return bool(self._lib.og_fused_used(self._ctx))
 
     def resident_for_budget(self, B, n_t, budget_bytes):
-        """Largest number of resident slices (up to n_t) whose workspace
-        fits in budget_bytes, 0 when none fits; leaves the setting at 0."""
+        """A number of resident slices (up to n_t) whose workspace fits in
+        budget_bytes, 0 when none fits; leaves the setting at 0.  The
+        workspace grows with the resident count except near n_t, where the
+        checkpoints it replaces can outweigh packed resident states: n_t
+        itself is tried first, then the largest count found by bisection."""
         def ws(r):
             self.set_resident(r)
             return self.workspace_bytes(B, n_t)
         lo, hi = 0, int(n_t)
-        if ws(0) > budget_bytes:
+        if ws(hi) <= budget_bytes:
+            lo = hi
+        elif ws(0) > budget_bytes:
             lo = 0
         else:
-            while lo < hi:  # largest r with ws(r) <= budget (ws grows with r)
+            while lo < hi:  # ws(lo) <= budget throughout
                 mid = (lo + hi + 1) // 2
                 if ws(mid) <= budget_bytes:
                     lo = mid

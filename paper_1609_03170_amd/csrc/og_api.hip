@@ -355,10 +355,17 @@ struct Engine : EngineBase {
   og_ctx* ctx;
   int d, K, J;
   bool banded;
-  long E;  // elements per matrix
+  long E;   // elements per matrix
+  long EH;  // elements of a packed Hermitian half, d (d + 1) / 2
   DirDev<T> dir[2];
   og::HBand<T> hband{};
   og::cpx<T>* hHd = nullptr;   // banded H_k diagonals
+  // weights of the Hermitian-half contraction (band_contract_half_kernel)
+  // by kind of offset o in (0, +1, -1, +N, -N): fhw[a][k][kind] =
+  // H_k[a - o, a]; half_ok when the H_k allow that contraction
+  og::cpx<T>* fhw = nullptr;
+  bool half_ok = false;
+  int half_k0 = 0;  // some H_k has a diagonal term
   // fused RK4 step (rk4_fused_kernel) per direction, when the operators have
   // the multi-level x oscillator structure it needs
   bool fused[2] = {false, false};
@@ -421,7 +428,8 @@ struct Engine : EngineBase {
   double* grad;
   double* pen;  // per-problem penalty traces Tr(A rho_n), n = 0..N_t
 
-  Engine(og_ctx* c) : ctx(c), d(c->d), K(c->K), J(c->J), banded(c->path == OG_PATH_BANDED), E((long)c->d * c->d) {}
+  Engine(og_ctx* c) : ctx(c), d(c->d), K(c->K), J(c->J), banded(c->path == OG_PATH_BANDED), E((long)c->d * c->d),
+                         EH((long)c->d * (c->d + 1) / 2) {}
 
   // Dense GEMMs: float32/float64 matrix-core GEMM, or for the split
   // precisions the 16-bit three-product split GEMM (float32 storage).
@@ -448,6 +456,7 @@ struct Engine : EngineBase {
         if (p) (void)hipFree(p);
     }
     if (hHd) (void)hipFree(hHd);
+    if (fhw) (void)hipFree(fhw);
     if (HT) (void)hipFree(HT);
     for (int s = 0; s < 2; ++s)
       for (void* p : {(void*)fa0[s], (void*)fak[s], (void*)fdl[s], (void*)fdr[s]})
@@ -644,11 +653,53 @@ struct Engine : EngineBase {
       for (auto& m : Hk) hv.push_back(dia_values(m, offs));
       OG_TRY(upload<T>(concat(hv), &hHd));
       hband.Hd = hHd;
+      OG_TRY(half_setup(offs, hv));
     } else {
       std::vector<std::vector<cd>> ht;
       for (auto& m : Hk) ht.push_back(transpose(m).a);
       OG_TRY(upload<T>(concat(ht), &HT));
     }
+    return OG_OK;
+  }
+
+  // The Hermitian-half contraction needs both directions fused (their level
+  // count nq and level size N), K <= FCK, every diagonal offset of the H_k
+  // one of 0, +1, -1, +N, -N and the +-1 diagonals zero where they cross
+  // from one level block to the next.
+  og_status half_setup(const std::vector<int>& offs, const std::vector<std::vector<cd>>& hv) {
+    half_ok = false;
+    if (!(fused[FWD] && fused[ADJ]) || K < 1 || K > og::FCK) return OG_OK;
+    const int Nn = fgeo[ADJ].N, nq = fgeo[ADJ].nq;
+    const int ko[5] = {0, 1, -1, Nn, -Nn};
+    std::vector<int> kind(offs.size(), -1);
+    for (size_t t = 0; t < offs.size(); ++t) {
+      for (int a = 0; a < (nq > 1 ? 5 : 3); ++a)
+        if (offs[t] == ko[a]) kind[t] = a;
+      if (kind[t] < 0) return OG_OK;
+    }
+    for (int k = 0; k < K; ++k)
+      for (size_t t = 0; t < offs.size(); ++t)
+        for (int a = 0; a < d; ++a) {
+          const int b = a + offs[t];
+          const bool cross = (offs[t] == 1 || offs[t] == -1) && b >= 0 && b < d && (a / Nn) != (b / Nn);
+          if (cross && hv[k][t * d + a] != cd(0, 0)) return OG_OK;
+        }
+    // h(k, kind, a) = H_k[a, a + o_kind]
+    auto h = [&](int k, int a5, int a) {
+      cd v(0, 0);
+      if (a < 0 || a >= d) return v;
+      for (size_t t = 0; t < offs.size(); ++t)
+        if (kind[t] == a5) v += hv[k][t * d + a];
+      return v;
+    };
+    std::vector<cd> hw((size_t)d * og::FCK * 5, cd(0, 0));
+    for (int i = 0; i < d; ++i)
+      for (int k = 0; k < K; ++k)
+        for (int a5 = 0; a5 < 5; ++a5) hw[((size_t)i * og::FCK + k) * 5 + a5] = h(k, a5, i - ko[a5]);
+    OG_TRY(upload<T>(hw, &fhw));
+    half_k0 = 0;
+    for (size_t t = 0; t < offs.size(); ++t) half_k0 |= kind[t] == 0 ? 1 : 0;
+    half_ok = true;
     return OG_OK;
   }
 
@@ -728,7 +779,8 @@ struct Engine : EngineBase {
       sz[L_DPC] = kDpCtl * dpctl_bytes(b);
       sz[L_DPCK] = (size_t)nseg * b * 2 * sizeof(double);
     }
-    sz[L_TAIL] = ntail > 0 ? (size_t)(ntail + 1) * m : 0;
+    // the packed Hermitian half of every state when the contraction reads that
+    sz[L_TAIL] = ntail > 0 ? (size_t)(ntail + 1) * (half_contract() ? (size_t)b * EH * sizeof(og::cpx<T>) : m) : 0;
     if (banded && (fused[0] || fused[1]))
       sz[L_FCOEF] = 2 * (size_t)kCoefChunk * b * og::FSLOT * d * sizeof(og::cpx<T>);
     size_t pos = 0;
@@ -958,13 +1010,20 @@ struct Engine : EngineBase {
     }
   }
   int fused_used() const override { return use_fused(FWD) && use_fused(ADJ) ? 1 : 0; }
+  // First-order gradient with fused steps in both directions: the slice
+  // contraction reads the Hermitian half of rho_{j+1} in the fused step's
+  // level-interleaved order (band_contract_half_kernel), and the resident
+  // tail keeps only that half, packed, written by the forward steps.
+  bool half_contract() const { return fused_used() && ctx->opt.gmode != OG_GRAD_EXACT && half_ok; }
+  og::cpx<T>* hslot(og::cpx<T>* base, int idx) const { return base + (long)idx * B * EH; }
+
 
   // One fused RK4 step (the four nested stages in one launch) for the whole
   // batch: (ihi, ilo) -> (ohi, olo).  ohi must differ from ihi (other tiles
   // read the halo of the input while the output is written); olo may equal
   // ilo (every element's compensation term is read and written by one block).
   og_status fused_step(int dr, int jslice, const og::cpx<T>* ihi, const og::cpx<T>* ilo, og::cpx<T>* ohi,
-                       og::cpx<T>* olo, T h) {
+                       og::cpx<T>* olo, T h, og::cpx<T>* pk = nullptr) {
     OG_TRY(assemble_fused(dr, jslice));
     og::StageIO<T> io = io_base();
     io.in = ihi;
@@ -972,6 +1031,8 @@ struct Engine : EngineBase {
     io.slo = ilo;
     io.ohi = ohi;
     io.olo = olo;
+    io.pk = pk;  // the packed Hermitian half of the output as well
+    io.pk_s = EH;
     const og::cpx<T>* cf = fcoef[dr] + (size_t)(jslice - fc0[dr]) * B * og::FSLOT * d;
     const dim3 grid((unsigned)(B * fgeo[dr].ntile));
     const long pidx = ctx->prof_begin(st);
@@ -1007,12 +1068,18 @@ struct Engine : EngineBase {
   // n_sub RK4 steps of slice j in direction dr on the state (hi, lo) "in
   // place": with the fused step every step writes the other buffer of the
   // pair (hi, alt) and the two pointers are swapped, so hi holds the result.
-  og_status advance(int dr, int jslice, og::cpx<T>*& hi, og::cpx<T>* lo, og::cpx<T>*& alt) {
-    if (!use_fused(dr)) return rk_slice(dr, jslice, hi, lo, hi, lo);
+  // pk (fused steps only): the last step also writes the packed Hermitian
+  // half of the result there.
+  og_status advance(int dr, int jslice, og::cpx<T>*& hi, og::cpx<T>* lo, og::cpx<T>*& alt,
+                    og::cpx<T>* pk = nullptr) {
+    if (!use_fused(dr)) {
+      if (pk) return fail(OG_ERR_ARG, "internal: packed output without the fused step");
+      return rk_slice(dr, jslice, hi, lo, hi, lo);
+    }
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dt / nsub);
     for (int s = 0; s < nsub; ++s) {
-      OG_TRY(fused_step(dr, jslice, hi, lo, alt, lo, h));
+      OG_TRY(fused_step(dr, jslice, hi, lo, alt, lo, h, s == nsub - 1 ? pk : nullptr));
       std::swap(hi, alt);
     }
     return OG_OK;
@@ -1047,6 +1114,33 @@ struct Engine : EngineBase {
       OG_TRY(stage(dr, og::SM_STAGE, jslice, Zb, shi, slo, Za, nullptr, h / T(2)));
       OG_TRY(stage(dr, og::SM_FINAL, jslice, Za, shi, slo, ohi, olo, h));
     }
+    return OG_OK;
+  }
+
+  // g[:, j, :] = coef * 2 Im Tr(H_k X L) from the Hermitian half of X (packed
+  // or full) and the full L, in the fused step's level order.
+  og_status contract_half(int jslice, const og::cpx<T>* X, bool x_packed, const og::cpx<T>* Lm, double coef) {
+    if (K == 0) return OG_OK;
+    og::HalfPair<T> hp{};
+    hp.X = X;
+    hp.x_s = x_packed ? EH : E;
+    hp.x_packed = x_packed ? 1 : 0;
+    hp.L = Lm;
+    hp.l_s = E;
+    hp.coef = coef;
+    hp.hw = fhw;
+    hp.K = K;
+    hp.k0 = half_k0;
+    const dim3 cg((unsigned)(og::NCH * B));
+    const int N = fgeo[FWD].N;
+    switch (fgeo[FWD].nq) {
+      case 1: og::band_contract_half_kernel<T, 1><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
+      case 2: og::band_contract_half_kernel<T, 2><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
+      case 3: og::band_contract_half_kernel<T, 3><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
+      case 4: og::band_contract_half_kernel<T, 4><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
+      default: return fail(OG_ERR_ARG, "internal: Hermitian-half contraction without its level count");
+    }
+    OG_CHECK_LAUNCH();
     return OG_OK;
   }
 
@@ -1316,12 +1410,21 @@ struct Engine : EngineBase {
         OG_TRY(advance(FWD, j, cur_hi, cur_lo, Za));
       OG_TRY(penalty_trace(j + 1));
     }
+    const bool half = half_contract();
+    if (n_tail > 0 && half) {
+      // packed tail: the steps go on in the state buffers and also write the
+      // Hermitian half of rho_{j+1} to its slot
+      for (int k = 0; k < n_tail; ++k) {
+        OG_TRY(advance(FWD, jt + k, cur_hi, cur_lo, Za, hslot(tail, k + 1)));
+        OG_TRY(penalty_trace(jt + k + 1));
+      }
+    }
     if (cur_hi != cur_base) {  // the fused step left the state in the other buffer
       OG_TRY(copy_hi(cur_base, cur_hi));
       Za = cur_hi;
       cur_hi = cur_base;
     }
-    if (n_tail > 0) {
+    if (n_tail > 0 && !half) {
       // the tail runs on the stored states; the compensation term stays in
       // cur_lo (read and written at the same elements by the final stage)
       OG_TRY(copy_hi(slot(tail, 0), cur_hi));
@@ -1384,7 +1487,10 @@ struct Engine : EngineBase {
     coef_reset();
     coef_hint(ADJ, 0, n_t, false);
     coef_hint(FWD, jt, n_t, false);
-    for (int k = n_tail - 1; k >= 0; --k) OG_TRY(back_slice(jt + k, slot(tail, k), nullptr, slot(tail, k + 1)));
+    if (half_contract())
+      for (int k = n_tail - 1; k >= 0; --k) OG_TRY(back_slice(jt + k, nullptr, nullptr, hslot(tail, k + 1), true));
+    else
+      for (int k = n_tail - 1; k >= 0; --k) OG_TRY(back_slice(jt + k, slot(tail, k), nullptr, slot(tail, k + 1)));
     for (int seg = n_seg - 1; seg >= 0; --seg) {
       const int j0 = seg * S, j1 = std::min(jt, j0 + S), n = j1 - j0;
       coef_hint(FWD, j0, j1, true);
@@ -1410,17 +1516,24 @@ struct Engine : EngineBase {
   }
 
   // One slice j of the backward sweep: the gradient contraction and the
-  // adjoint step, from rho_j (r_hi, r_lo) and rho_{j+1} (r1_hi).
-  og_status back_slice(int j, const og::cpx<T>* r_hi, const og::cpx<T>* r_lo, const og::cpx<T>* r1_hi) {
+  // adjoint step, from rho_j (r_hi, r_lo) and rho_{j+1} (r1_hi; its packed
+  // Hermitian half when r1_packed).
+  og_status back_slice(int j, const og::cpx<T>* r_hi, const og::cpx<T>* r_lo, const og::cpx<T>* r1_hi,
+                       bool r1_packed = false) {
     const bool exact = ctx->opt.gmode == OG_GRAD_EXACT;
     const int nsub = ctx->opt.n_sub;
     const T h = (T)(dt / nsub);
     const bool ad = ctx->ad_rtol > 0.0;
     if (!exact) {
-      const og::cpx<T>* Xs[1] = {r1_hi};
-      const og::cpx<T>* Ls[1] = {lam_hi};
-      const double cf[1] = {dt};
-      OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
+      if (half_contract()) {
+        OG_TRY(contract_half(j, r1_hi, r1_packed, lam_hi, dt));
+      } else {
+        if (r1_packed) return fail(OG_ERR_ARG, "internal: packed state without the half contraction");
+        const og::cpx<T>* Xs[1] = {r1_hi};
+        const og::cpx<T>* Ls[1] = {lam_hi};
+        const double cf[1] = {dt};
+        OG_TRY(contract(j, 1, Xs, Ls, cf, 0));
+      }
       if (ad)
         OG_TRY(adaptive_slice(ADJ, j, lam_hi, lam_lo, dpc[DP_ADJ]));
       else
@@ -1601,7 +1714,15 @@ struct Engine : EngineBase {
           ps.out[q] = sl.part + (long)o.slice * og::NCH * K;
         }
         const dim3 cg((unsigned)(og::NCH * m));
-        if (hband.nH <= 4)
+        const int hN = fgeo[FWD].N;
+        if (half_contract()) {  // the same arithmetic as the batch entry points
+          switch (fgeo[FWD].nq) {
+            case 1: og::band_contract_half_slots_kernel<T, 1><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
+            case 2: og::band_contract_half_slots_kernel<T, 2><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
+            case 3: og::band_contract_half_slots_kernel<T, 3><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
+            default: og::band_contract_half_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
+          }
+        } else if (hband.nH <= 4)
           og::band_contract_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);
         else if (hband.nH <= 8)
           og::band_contract_slots_kernel<T, 8><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);

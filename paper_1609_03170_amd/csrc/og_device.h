@@ -122,6 +122,8 @@ struct StageIO {
   long o_s;
   const cpx<T>* ex[3];  // extra terms added to the increment (SM_FINAL)
   long ex_s;
+  cpx<T>* pk;         // fused step: packed Hermitian half of the output (nullptr: none)
+  long pk_s;
   int nex;
   T coef;
   int* status;        // set to 1 when a non-finite value is produced
@@ -255,6 +257,7 @@ struct ProbPtr {
   cpx<T>* ohi;
   cpx<T>* olo;
   const cpx<T>* ex[3];
+  cpx<T>* pk;
 };
 
 template <typename T>
@@ -267,6 +270,7 @@ __device__ __forceinline__ ProbPtr<T> resolve_strided(const StageIO<T>& io, int 
   P.olo = io.olo ? io.olo + (long)b * io.o_s : nullptr;
 #pragma unroll
   for (int x = 0; x < 3; ++x) P.ex[x] = io.ex[x] ? io.ex[x] + (long)b * io.ex_s : nullptr;
+  P.pk = io.pk ? io.pk + (long)b * io.pk_s : nullptr;
   return P;
 }
 
@@ -762,6 +766,15 @@ __device__ __forceinline__ int2 fused_tile(int t, int nb) {
 }
 
 
+// Packed Hermitian half of a d x d matrix in the level-interleaved order
+// p = n NQ + q of index i = q N + n (the order of the fused step's
+// canonical elements, p <= p'): row p holds columns p .. d - 1, rows one
+// after the other, d (d + 1) / 2 elements in all.
+__host__ __device__ __forceinline__ long half_row_start(int p, int d) {
+  return (long)p * d - (long)p * (p - 1) / 2;
+}
+__host__ __device__ __forceinline__ long half_index(int p, int pc, int d) { return half_row_start(p, d) + (pc - p); }
+
 // Coefficients of the fused step for slices jslice .. jslice + gridDim.z - 1
 // and every problem b (gridDim.y): out[z][b][i][FSLOT] = the diagonals of
 // A(u_j) = A0 + sum_k u[b, j, k] Ak at row i (slots 0..4) and the row
@@ -834,6 +847,10 @@ __device__ __forceinline__ cpx<T> fused_coef_at(const FusedOps<T>& fo, const dou
   }
   return v;
 }
+
+// Controls of the Hermitian-half gradient contraction (at most): its
+// weight tables hold FCK x 5 entries per index.
+constexpr int FCK = 4;
 
 // With LC (the serving launches) the coefficients are formed by the block
 // itself from fo and the slice's controls ub: the rows of its window into
@@ -1081,6 +1098,7 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
           bad |= !(isfinite(hi.re) && isfinite(hi.im));
           P.ohi[e] = hi;
           if (comp) lo_st(P.olo, e, lo);
+          if (P.pk) P.pk[half_index(nr * NQ + q, n_c * NQ + qc, d)] = hi;
         }
       }
     }
@@ -1174,6 +1192,7 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 3 : 2) void rk4_fused_slo
   P.ohi = s.o_hi;
   P.olo = s.o_lo;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
+  P.pk = nullptr;
   rk4_fused_body<T, NQ, NW, S, true>(g, P, nullptr, drt, h, status, t, d, buf, fo, s.urow);
 }
 
@@ -1748,6 +1767,239 @@ __global__ __launch_bounds__(256) void band_contract_slots_kernel(PairSlots<T> p
 #pragma unroll
   for (int k = 0; k < MAXK; ++k) acc[k] = 0.0;
   contract_rows<T, NH>(ps.X[b], ps.L[b], cf, hb, K, d, a0, a1, acc);
+  write_partials(sh, acc, K, ps.out[b], (long)ch * K, 0);
+}
+
+// Gradient contraction of one pair (X, L), both Hermitian, from the
+// Hermitian half of X only (first-order gradient with fused steps):
+//   Tr(H_k X L) = sum over the half (b, c) of
+//     X[b, c] sum_o conj(L[b - o, c]) h_ko(b - o)
+//     + (b != c) conj(X[b, c]) sum_o L[b, c - o] h_ko(c - o),
+// h_ko(a) = H_k[a, a + o], o in {0, +1, -1, +N, -N} (kinds 0..4).  In the
+// level-interleaved order p = n nq + q of index q N + n these offsets are
+// the shifts 0, -nq, +nq, -1, +1 of p (the +-1 diagonals are zero across a
+// level block, and a shift out of a level meets a zero weight), so the taps
+// of a tile of L lie in the tile widened by nq on every side.
+// Work unit: HT_ROWS rows p by 64 CG columns p'.  The block stages L's
+// widened tile in LDS (zeros outside the matrix and left of the rows'
+// diagonal), each wave takes every fourth row and each lane CG columns;
+// the first sum is weighted per row once the lane's CG columns are added,
+// the second per column once the unit's rows are added (the four waves'
+// sums added in LDS).  X is the packed half (x_packed) or a full matrix
+// read on the half.  Weights hw[a][k][kind] = h_k,kind(a - o_kind).
+template <typename T>
+struct HalfPair {
+  const cpx<T>* X;
+  long x_s;
+  int x_packed;
+  const cpx<T>* L;
+  long l_s;
+  double coef;
+  const cpx<T>* hw;  // [d][FCK][5]
+  int K;
+  int k0;  // some H_k has a diagonal (offset 0) term
+};
+
+constexpr int HT_ROWS = 16;  // rows per work unit (four per wave)
+template <typename T>
+constexpr int half_cg() { return sizeof(T) == 8 ? 1 : 2; }  // columns per lane
+template <typename T, int NQ>
+constexpr int half_wc() { return 64 * half_cg<T>() + 2 * NQ; }  // LDS row of the widened tile
+template <typename T, int NQ>
+constexpr int half_lds_elems() {
+  constexpr int win = (HT_ROWS + 2 * NQ) * half_wc<T, NQ>();
+  constexpr int red = 4 * half_cg<T>() * 5 * 64;  // the waves' column sums (after the window is read)
+  return (win > red ? win : red) + HT_ROWS * FCK * 5;
+}
+
+// acc[k] += coef * (the 2-less Im part of chunk ch's share of Tr(H_k X L)).
+template <typename T, int NQ>
+__device__ __forceinline__ void contract_half_chunk(const cpx<T>* __restrict__ X, int x_packed,
+                                                    const cpx<T>* __restrict__ L, double coef, int N,
+                                                    const cpx<T>* __restrict__ hw, int k0, int d, int ch,
+                                                    double* acc, cpx<T>* __restrict__ sm) {
+  constexpr int CG = half_cg<T>(), TC = 64 * CG, WC = half_wc<T, NQ>();
+  constexpr int WR = HT_ROWS + 2 * NQ, NWIN = WR * WC;
+  constexpr int NK = NQ > 1 ? 5 : 3;
+  constexpr int DK[5] = {0, -NQ, NQ, -1, 1};  // the shift of p (rows) or p' (columns) of each kind
+  cpx<T>* __restrict__ win = sm;
+  cpx<T>* __restrict__ wrow = sm + (NWIN > 4 * CG * 5 * 64 ? NWIN : 4 * CG * 5 * 64);  // [HT_ROWS][FCK][5]
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // index q N + n of level-interleaved position p = n NQ + q
+  auto lidx = [&](int pp) { return (pp % NQ) * N + pp / NQ; };
+  const int nct = (d + TC - 1) / TC;
+  int ct = 0, cu0 = 0;  // column tile of unit u, its first unit
+  auto nrt = [&](int c) { return (min(d, (c + 1) * TC) + HT_ROWS - 1) / HT_ROWS; };
+  for (int u = ch;; u += NCH) {
+    while (ct < nct && u >= cu0 + nrt(ct)) cu0 += nrt(ct++);
+    if (ct >= nct) break;
+    const int c0 = ct * TC, r0 = (u - cu0) * HT_ROWS;
+    const int rend = min(d, r0 + HT_ROWS);
+    // ---- this wave's X; the widened tile of L and the rows' weights -> LDS
+    // (loads issued in batches; zeroed by a factor, since a select lets the
+    // compiler move a load under a branch whose zero path waits for it) ----
+    int xcol[CG];  // index of this lane's column of each group
+#pragma unroll
+    for (int g = 0; g < CG; ++g) xcol[g] = lidx(min(c0 + 64 * g + lane, d - 1));
+    cpx<T> x[4][CG];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int p = r0 + wave + 4 * m;
+      const long xrow = x_packed ? half_row_start(p, d) - p : (long)lidx(min(p, d - 1)) * d;
+#pragma unroll
+      for (int g = 0; g < CG; ++g) {
+        const int pc = c0 + 64 * g + lane;
+        const bool act = p < rend && pc >= p && pc < d;
+        x[m][g] = act ? X[x_packed ? xrow + pc : xrow + xcol[g]] : mkc<T>(0, 0);
+      }
+    }
+    // window rows by wave, columns by lane: the column indices once per unit
+    constexpr int NCJ = (WC + 63) / 64, RPW = (WR + 3) / 4, RB = sizeof(T) == 8 ? 2 : 3;
+    int coff[NCJ];
+    T cok[NCJ];
+#pragma unroll
+    for (int j = 0; j < NCJ; ++j) {
+      const int wc = lane + 64 * j, pc = c0 - NQ + wc;
+      const int lo = max(r0 - NQ, 0);  // columns left of the rows' diagonal are never read
+      coff[j] = lidx(min(max(pc, lo), d - 1));
+      cok[j] = wc < WC && pc >= lo && pc < d ? T(1) : T(0);
+    }
+#pragma unroll
+    for (int m0 = 0; m0 < RPW; m0 += RB) {
+      cpx<T> v[RB][NCJ];
+#pragma unroll
+      for (int m = 0; m < RB; ++m) {
+        const int wr = wave + 4 * (m0 + m), p = r0 - NQ + wr;
+        const cpx<T>* __restrict__ Lr = L + (long)lidx(min(max(p, 0), d - 1)) * d;
+        const T rok = m0 + m < RPW && wr < WR && p >= 0 && p < d ? T(1) : T(0);
+#pragma unroll
+        for (int j = 0; j < NCJ; ++j) {
+          const cpx<T> lv = Lr[coff[j]];
+          const T k = rok * cok[j];
+          v[m][j] = mkc<T>(lv.re * k, lv.im * k);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < RB; ++m) {
+        const int wr = wave + 4 * (m0 + m);
+#pragma unroll
+        for (int j = 0; j < NCJ; ++j)
+          if (m0 + m < RPW && wr < WR && lane + 64 * j < WC) win[wr * WC + lane + 64 * j] = v[m][j];
+      }
+    }
+    {
+      constexpr int NW2 = (HT_ROWS * FCK * 5 + 255) / 256;
+      cpx<T> v[NW2];
+#pragma unroll
+      for (int f = 0; f < NW2; ++f) {
+        const int e = f * 256 + tid, r = e / (FCK * 5);
+        const cpx<T> hv = hw[(long)lidx(min(r0 + r, d - 1)) * (FCK * 5) + (min(e, HT_ROWS * FCK * 5 - 1) - r * FCK * 5)];
+        const T keep = e < HT_ROWS * FCK * 5 && r0 + r < rend ? T(1) : T(0);
+        v[f] = mkc<T>(hv.re * keep, hv.im * keep);
+      }
+#pragma unroll
+      for (int f = 0; f < NW2; ++f)
+        if (f * 256 + tid < HT_ROWS * FCK * 5) wrow[f * 256 + tid] = v[f];
+    }
+    __syncthreads();
+    // ---- products: rows of this wave, CG columns per lane ----
+    cpx<T> R[CG][NK];
+#pragma unroll
+    for (int g = 0; g < CG; ++g)
+#pragma unroll
+      for (int a = 0; a < NK; ++a) R[g][a] = mkc<T>(0, 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int p = r0 + wave + 4 * m;
+      if (p >= rend) break;  // wave-uniform
+      cpx<T> Q[NK];
+#pragma unroll
+      for (int a = 0; a < NK; ++a) Q[a] = mkc<T>(0, 0);
+#pragma unroll
+      for (int g = 0; g < CG; ++g) {
+        if (c0 + 64 * g + 63 < p) continue;  // the whole group left of the diagonal (wave-uniform)
+        const int pc = c0 + 64 * g + lane;
+        const cpx<T>* __restrict__ wp = win + (p - r0 + NQ) * WC + 64 * g + lane + NQ;
+        const cpx<T> xv = x[m][g];
+        const cpx<T> xo = pc != p ? xv : mkc<T>(0, 0);  // the mirror of an off-diagonal element only
+#pragma unroll
+        for (int a = 0; a < NK; ++a) {
+          if (a == 0 && !k0) continue;      // no diagonal term among the H_k
+          cfmac(Q[a], xv, wp[DK[a] * WC]);  // x conj(L[b - o, c])
+          cfmac(R[g][a], wp[DK[a]], xo);    // L[b, c - o] conj(x)
+        }
+      }
+      // row weights h_k,kind(b - o)
+      const cpx<T>* __restrict__ w = wrow + (p - r0) * (FCK * 5);
+#pragma unroll
+      for (int k = 0; k < FCK; ++k) {
+        T sw = 0;
+#pragma unroll
+        for (int a = k0 ? 0 : 1; a < NK; ++a) sw = fmad(w[k * 5 + a].re, Q[a].im, fmad(w[k * 5 + a].im, Q[a].re, sw));
+        acc[k] += coef * (double)sw;
+      }
+    }
+    // ---- column weights h_k,kind(c - o): the waves' sums added in LDS ----
+    __syncthreads();  // the window is read
+    cpx<T>* __restrict__ red = sm;
+#pragma unroll
+    for (int g = 0; g < CG; ++g)
+#pragma unroll
+      for (int a = 0; a < NK; ++a) red[((wave * CG + g) * 5 + a) * 64 + lane] = R[g][a];
+    __syncthreads();
+    for (int g = wave; g < CG; g += 4) {
+      const int pc = c0 + 64 * g + lane;
+      if (pc < d) {
+        const cpx<T>* __restrict__ hc = hw + (long)lidx(pc) * (FCK * 5);
+#pragma unroll
+        for (int a = 0; a < NK; ++a) {
+          if (a == 0 && !k0) continue;
+          cpx<T> Rs = red[(g * 5 + a) * 64 + lane];
+#pragma unroll
+          for (int w2 = 1; w2 < 4; ++w2) Rs = cadd(Rs, red[((w2 * CG + g) * 5 + a) * 64 + lane]);
+#pragma unroll
+          for (int k = 0; k < FCK; ++k) {
+            const cpx<T> hv = hc[k * 5 + a];
+            acc[k] += coef * (double)fmad(hv.re, Rs.im, hv.im * Rs.re);
+          }
+        }
+      }
+    }
+    __syncthreads();  // the sums are read before the next unit's window is stored
+  }
+}
+
+template <typename T, int NQ>
+__global__ __launch_bounds__(256) void band_contract_half_kernel(HalfPair<T> hp, int N, int d,
+                                                                 double* __restrict__ part, long n_t, int jslice) {
+  __shared__ double sh[4][MAXK];
+  __shared__ cpx<T> sm[half_lds_elems<T, NQ>()];
+  // the chunks of one problem share an XCD (and its L2): their taps reach
+  // into each other's rows
+  const int Lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = Lb / NCH, ch = Lb - b * NCH;
+  double acc[FCK];
+#pragma unroll
+  for (int k = 0; k < FCK; ++k) acc[k] = 0.0;
+  contract_half_chunk<T, NQ>(hp.X + (long)b * hp.x_s, hp.x_packed, hp.L + (long)b * hp.l_s, hp.coef, N, hp.hw,
+                             hp.k0, d, ch, acc, sm);
+  write_partials(sh, acc, hp.K, part, (((long)b * n_t + jslice) * NCH + ch) * hp.K, 0);
+}
+
+// Slot-table variant (serving): full X and L of slot b, partials to
+// out[b][chunk][k].
+template <typename T, int NQ>
+__global__ __launch_bounds__(256) void band_contract_half_slots_kernel(PairSlots<T> ps, double cf,
+                                                                       const cpx<T>* __restrict__ hw, int k0, int K,
+                                                                       int N, int d) {
+  __shared__ double sh[4][MAXK];
+  __shared__ cpx<T> sm[half_lds_elems<T, NQ>()];
+  const int Lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int b = Lb / NCH, ch = Lb - b * NCH;
+  double acc[FCK];
+#pragma unroll
+  for (int k = 0; k < FCK; ++k) acc[k] = 0.0;
+  contract_half_chunk<T, NQ>(ps.X[b], 0, ps.L[b], cf, N, hw, k0, d, ch, acc, sm);
   write_partials(sh, acc, K, ps.out[b], (long)ch * K, 0);
 }
 

@@ -70,9 +70,15 @@ def test_resident_workspace_budget_and_serving_refusal():
     w = wl.config_c3(batch=2, n_t=50)
     p = Problem.from_workload(w, prec="f32")
     w0 = p.workspace_bytes(2, 50)
-    state = 2 * w.d * w.d * 8
+    # with fused steps and the first-order gradient a resident state is its
+    # packed Hermitian half, d (d + 1) / 2 elements
+    assert p.fused
+    state = 2 * (w.d * (w.d + 1) // 2) * 8
     p.set_resident(50)  # all 51 states resident, no checkpoints
-    assert p.workspace_bytes(2, 50) >= 51 * state and p.workspace_bytes(2, 50) > w0
+    assert p.workspace_bytes(2, 50) >= 51 * state
+    p.set_fused(False)  # full states on the four-stage path
+    assert p.workspace_bytes(2, 50) >= 51 * 2 * w.d * w.d * 8
+    p.set_fused(True)
     budget = w0 + 10 * state
     r = p.resident_for_budget(2, 50, budget)
     assert r >= 5
