@@ -180,6 +180,12 @@ def fused_roofline(r, d):
     flops = B * 4.0 * herm * FLOP_PER_ELEM_STAGE
     s = 8 if r["prec"] == "f32" else 16
     hbm_bytes = B * d * d * (2 * s + ((2 + 4) if r["prec"] == "f32" else 0))
+    # the forward steps of the resident slices also write the packed
+    # Hermitian half of their state (first-order gradient): averaged over the
+    # evaluation's launches (forward N_t, recompute N_t - resident, adjoint N_t)
+    n_t, res = r.get("n_t"), r.get("resident_slices", 0)
+    if n_t and res and r.get("gradient") == "grape1":
+        hbm_bytes += B * herm * s * res / (3.0 * n_t - res)
     stage_model = B * 4 * 2.0 * d * d * s  # four stage kernels, each reading and writing the state once
     t = us * 1e-6
     return {"bound": "alu", "kernel": "rk4_fused_kernel", "achieved": flops / t / 1e12, "peak": VALU_PEAK_TFLOPS,
@@ -311,7 +317,7 @@ def run_gpu(args, prec, w, golden, batch=None, steps=None, warmup=None, path=Non
     g = g.cpu().numpy()
     out = dict(prec=prec, batch=B, steps=steps, elapsed=elapsed, ms_per_step=1000 * elapsed / steps,
                value=B * steps / elapsed, kern_us=kern_us, kern_n=kern_n, path=p.path, gradient=gmode,
-               fused=p.fused, resident_slices=res, workspace_gib=ws_gib)
+               fused=p.fused, resident_slices=res, workspace_gib=ws_gib, n_t=n_t)
     if autograd:
         out["interface"] = "OpenGrapeCost (torch.autograd.Function)"
     if stats is not None:

@@ -175,8 +175,12 @@ og_status og_set_adaptive(og_ctx *ctx, double rtol, double atol);
  * only the slices before them from checkpoints (every ckpt_stride slices of
  * those, default ceil(sqrt(N_t - n_slices))).  n_slices = 0 (the default)
  * keeps none; values above N_t keep all.  og_workspace_bytes grows by
- * (min(n_slices, N_t) + 1) state matrices per problem (working precision,
- * no compensation term); query it after this call.  Results are bitwise
+ * (min(n_slices, N_t) + 1) states per problem (working precision, no
+ * compensation term): with the first-order gradient and fused steps in
+ * both directions (og_fused_used) each is the packed Hermitian half of
+ * rho_j, d (d + 1) / 2 elements, else a full d x d matrix; query it after
+ * this call (the packed half can make the workspace with every slice
+ * resident smaller than the one with checkpoints).  Results are bitwise
  * those without resident states.  Used with fixed steps, and for
  * OG_GRAD_EXACT only with n_sub = 1 (ignored otherwise); servers refuse
  * requests while it is set.  OG_ERR_ARG for n_slices < 0 or a NULL ctx.
