@@ -372,7 +372,12 @@ struct Engine : EngineBase {
   og::FusedGeo fgeo[2]{};
   size_t fused_lds[2] = {0, 0};
   size_t fused_lds_slots[2] = {0, 0};  // serving launches: + the coefficient rows of the window
-  static constexpr int kFusedNW = sizeof(T) == 4 ? 4 : 8;  // waves per block
+  // waves per fused-step block: 8 in float64; in float32 4 (four blocks per
+  // CU), or 8 for grids of fewer than kFusedSmall blocks, which fill less
+  // than one round of the chip and wait on each block's own latency
+  // (measured at d = 240: 8 waves 22 / 27 / 40 us at 21 / 336 / 672 blocks
+  // against 32 / 34 / 40 us with 4; 4 waves ahead from 1008 blocks on)
+  static constexpr int kFusedSmall = 768;
   // fused-step coefficient data per direction: A0 and A_k on the five
   // diagonals (0, +1, -1, -N, +N) row by row (d x 5, K x d x 5), the row
   // (d x 3) and column (d x FDR) factors of the dissipator taps
@@ -994,19 +999,27 @@ struct Engine : EngineBase {
   // Call f(levels, sign) with the compile-time level count (1..4) and tap
   // sign (+-1) of direction dr's fused step.
   template <typename F>
-  void fused_dispatch(int dr, F&& f) {
+  void fused_dispatch(int dr, long blocks, F&& f) {
+    using std::integral_constant;
+    if (sizeof(T) == 4 && blocks >= kFusedSmall)
+      fused_dispatch_nw(dr, f, integral_constant<int, 4>{});
+    else
+      fused_dispatch_nw(dr, f, integral_constant<int, 8>{});
+  }
+  template <typename F, typename NW>
+  void fused_dispatch_nw(int dr, F& f, NW nw) {
     using std::integral_constant;
     const int nq = fgeo[dr].nq, sg = fgeo[dr].s1;
     if (sg > 0) {
-      if (nq == 1) f(integral_constant<int, 1>{}, integral_constant<int, 1>{});
-      else if (nq == 2) f(integral_constant<int, 2>{}, integral_constant<int, 1>{});
-      else if (nq == 3) f(integral_constant<int, 3>{}, integral_constant<int, 1>{});
-      else f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
+      if (nq == 1) f(integral_constant<int, 1>{}, integral_constant<int, 1>{}, nw);
+      else if (nq == 2) f(integral_constant<int, 2>{}, integral_constant<int, 1>{}, nw);
+      else if (nq == 3) f(integral_constant<int, 3>{}, integral_constant<int, 1>{}, nw);
+      else f(integral_constant<int, 4>{}, integral_constant<int, 1>{}, nw);
     } else {
-      if (nq == 1) f(integral_constant<int, 1>{}, integral_constant<int, -1>{});
-      else if (nq == 2) f(integral_constant<int, 2>{}, integral_constant<int, -1>{});
-      else if (nq == 3) f(integral_constant<int, 3>{}, integral_constant<int, -1>{});
-      else f(integral_constant<int, 4>{}, integral_constant<int, -1>{});
+      if (nq == 1) f(integral_constant<int, 1>{}, integral_constant<int, -1>{}, nw);
+      else if (nq == 2) f(integral_constant<int, 2>{}, integral_constant<int, -1>{}, nw);
+      else if (nq == 3) f(integral_constant<int, 3>{}, integral_constant<int, -1>{}, nw);
+      else f(integral_constant<int, 4>{}, integral_constant<int, -1>{}, nw);
     }
   }
   int fused_used() const override { return use_fused(FWD) && use_fused(ADJ) ? 1 : 0; }
@@ -1036,9 +1049,10 @@ struct Engine : EngineBase {
     const og::cpx<T>* cf = fcoef[dr] + (size_t)(jslice - fc0[dr]) * B * og::FSLOT * d;
     const dim3 grid((unsigned)(B * fgeo[dr].ntile));
     const long pidx = ctx->prof_begin(st);
-    fused_dispatch(dr, [&](auto nq, auto sg) {
-      og::rk4_fused_kernel<T, decltype(nq)::value, kFusedNW, decltype(sg)::value>
-          <<<grid, kFusedNW * 64, fused_lds[dr], st>>>(fgeo[dr], io, d, cf, fdr[dr], h);
+    fused_dispatch(dr, (long)grid.x, [&](auto nq, auto sg, auto nw) {
+      constexpr int NW = decltype(nw)::value;
+      og::rk4_fused_kernel<T, decltype(nq)::value, NW, decltype(sg)::value>
+          <<<grid, NW * 64, fused_lds[dr], st>>>(fgeo[dr], io, d, cf, fdr[dr], h);
     });
     OG_CHECK_LAUNCH();
     ctx->prof_end(pidx, st);
@@ -1778,10 +1792,11 @@ struct Engine : EngineBase {
         }
         const dim3 grid((unsigned)(n * fgeo[dr].ntile));
         const long pidx = ctx->prof_begin(st);
-        fused_dispatch(dr, [&](auto nq, auto sg) {
-          og::rk4_fused_slots_kernel<T, decltype(nq)::value, kFusedNW, decltype(sg)::value>
-              <<<grid, kFusedNW * 64, fused_lds_slots[dr], st>>>(fgeo[dr], ft, fops(dr), fdr[dr], h,
-                                                                 ctx->status_dev, d);
+        fused_dispatch(dr, (long)grid.x, [&](auto nq, auto sg, auto nw) {
+          constexpr int NW = decltype(nw)::value;
+          og::rk4_fused_slots_kernel<T, decltype(nq)::value, NW, decltype(sg)::value>
+              <<<grid, NW * 64, fused_lds_slots[dr], st>>>(fgeo[dr], ft, fops(dr), fdr[dr], h, ctx->status_dev,
+                                                           d);
         });
         OG_CHECK_LAUNCH();
         ctx->prof_end(pidx, st);

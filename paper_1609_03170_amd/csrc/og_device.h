@@ -1146,7 +1146,7 @@ __device__ __forceinline__ void rk4_fused_body(const FusedGeo& g, const ProbPtr<
 // the problems' rows of FSLOT coefficients (fused_coef_kernel), drt the
 // column factors of the dissipator taps (d x FDR).
 template <typename T, int NQ, int NW, int S>
-__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 4 : 2) void rk4_fused_kernel(FusedGeo g, StageIO<T> io, int d,
+__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 && NW == 4 ? 4 : 2) void rk4_fused_kernel(FusedGeo g, StageIO<T> io, int d,
                                                             const cpx<T>* __restrict__ coef,
                                                             const cpx<T>* __restrict__ drt, T h) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
@@ -1177,7 +1177,7 @@ struct FusedSlotTable {
 };
 
 template <typename T, int NQ, int NW, int S>
-__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 ? 3 : 2) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
+__global__ __launch_bounds__(NW * 64, sizeof(T) == 4 && NW == 4 ? 3 : 2) void rk4_fused_slots_kernel(FusedGeo g, FusedSlotTable<T> tab,
                                                                   FusedOps<T> fo, const cpx<T>* __restrict__ drt,
                                                                   T h, int* status, int d) {
   extern __shared__ __align__(16) unsigned char fused_smem[];
