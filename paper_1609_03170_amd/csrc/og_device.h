@@ -1305,13 +1305,18 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  acc_t cr[2][2], ci[2][2];
+  // float64: four real products per complex product (cr = Re, ci = Im);
+  // float32: three (cr = Re A Re B, ci = Im A Im B, cs = (Re A + Im A)(Re B + Im B);
+  // Re = cr - ci, Im = cs - cr - ci)
+  constexpr bool G3 = sizeof(T) == 4;
+  acc_t cr[2][2], ci[2][2], cs[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       cr[a][c] = acc_t{0, 0, 0, 0};
       ci[a][c] = acc_t{0, 0, 0, 0};
+      cs[a][c] = acc_t{0, 0, 0, 0};
     }
   // the operands of the next K step are loaded into registers while the
   // matrix cores work on the current one
@@ -1361,15 +1366,32 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
         br[a] = Br[kk][wn + a * 16 + (lane & 15)];
         bi[a] = Bi[kk][wn + a * 16 + (lane & 15)];
       }
+      if constexpr (G3) {
+        T as[2], bs[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          cr[a][c] = Mfma<T>::mma(ar[a], br[c], cr[a][c]);
-          cr[a][c] = Mfma<T>::mma(-ai[a], bi[c], cr[a][c]);
-          ci[a][c] = Mfma<T>::mma(ar[a], bi[c], ci[a][c]);
-          ci[a][c] = Mfma<T>::mma(ai[a], br[c], ci[a][c]);
+        for (int a = 0; a < 2; ++a) {
+          as[a] = ar[a] + ai[a];
+          bs[a] = br[a] + bi[a];
         }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            cr[a][c] = Mfma<T>::mma(ar[a], br[c], cr[a][c]);
+            ci[a][c] = Mfma<T>::mma(ai[a], bi[c], ci[a][c]);
+            cs[a][c] = Mfma<T>::mma(as[a], bs[c], cs[a][c]);
+          }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            cr[a][c] = Mfma<T>::mma(ar[a], br[c], cr[a][c]);
+            cr[a][c] = Mfma<T>::mma(-ai[a], bi[c], cr[a][c]);
+            ci[a][c] = Mfma<T>::mma(ar[a], bi[c], ci[a][c]);
+            ci[a][c] = Mfma<T>::mma(ai[a], br[c], ci[a][c]);
+          }
+      }
     }
     __syncthreads();
   }
@@ -1384,7 +1406,12 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
         const int row = m0 + wm + a * 16 + Mfma<T>::row(lane, v);
         const int col = n0 + wn + c * 16 + (lane & 15);
         if (row < M && col < N) {
-          const T xr = cr[a][c][v], xi = ci[a][c][v];
+          T xr = cr[a][c][v], xi = ci[a][c][v];
+          if constexpr (G3) {
+            const T p1 = xr, p2 = xi;
+            xr = p1 - p2;
+            xi = cs[a][c][v] - p1 - p2;
+          }
           cpx<T> o = mkc<T>(al.re * xr - al.im * xi, al.re * xi + al.im * xr);
           if (use_beta) cfma(o, be, C[(long)row * ldc + col]);
           C[(long)row * ldc + col] = o;
