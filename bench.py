@@ -60,7 +60,9 @@ def _parse():
                     help="the offered load that gets the full --serve-requests stream")
     ap.add_argument("--serve-side-requests", type=int, default=1024,
                     help="requests at the other offered loads")
-    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-resident", type=int, default=1,
+                    help="1: requests keep the packed halves of their forward states (no recompute)")
     ap.add_argument("--serve-slices", type=int, default=32, help="slices per request and server step")
     ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--workload", default="c3", choices=["c3", "c4"],
@@ -131,12 +133,12 @@ def serving_leg(args):
     reqs = wl.serving_requests(n_sat + max(n_main, n_side), seed=10, arrival_seed=9, rate=1.0)
     models = {s: wl.serving_model(s) for s in wl.SERVING_SHAPES}
     loop = ServingLoop(models, prec="f32", budget_bytes=int(args.serve_budget_gib * 2**30),
-                       max_slices=args.serve_slices)
+                       max_slices=args.serve_slices, resident=bool(args.serve_resident))
     _log(f"[serve] saturation run: {n_sat} requests at t=0")
     sat = loop.run([dict(r, arrival=0.0) for r in reqs[:n_sat]], wl.serving_controls, log=_log)
     thr = sat.throughput()
     out = {"saturation_req_per_s": thr, "saturation_requests": n_sat, "budget_gib": args.serve_budget_gib,
-           "fused": bool(loop.problems[next(iter(models))].fused),
+           "fused": bool(loop.problems[next(iter(models))].fused), "resident_states": bool(args.serve_resident),
            "workload": "Poisson stream, d in {20,40,90,160,240}, N_t ~ U[500,5000], dt=0.002, float32, "
                        "first-order gradient", "loads": []}
     tail = reqs[n_sat:]

@@ -182,8 +182,11 @@ og_status og_set_adaptive(og_ctx *ctx, double rtol, double atol);
  * this call (the packed half can make the workspace with every slice
  * resident smaller than the one with checkpoints).  Results are bitwise
  * those without resident states.  Used with fixed steps, and for
- * OG_GRAD_EXACT only with n_sub = 1 (ignored otherwise); servers refuse
- * requests while it is set.  OG_ERR_ARG for n_slices < 0 or a NULL ctx.
+ * OG_GRAD_EXACT only with n_sub = 1 (ignored otherwise).  Servers keep the
+ * last min(n_slices, n_t) states of each request the same way (packed
+ * halves only: with the first-order gradient and fused steps in both
+ * directions, else they refuse requests while it is set).  OG_ERR_ARG for
+ * n_slices < 0 or a NULL ctx.
  */
 og_status og_set_resident(og_ctx *ctx, int n_slices);
 

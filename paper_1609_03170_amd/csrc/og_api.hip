@@ -1612,12 +1612,17 @@ struct Engine : EngineBase {
   // contraction.  Requests at the same kind of slice operation share the
   // launches of one step.
   // -------------------------------------------------------------------------
-  enum { PH_FWD = 1, PH_RECOMP = 2, PH_ADJ = 3, PH_DONE = 4 };
+  enum { PH_FWD = 1, PH_RECOMP = 2, PH_ADJ = 3, PH_DONE = 4, PH_TAIL = 5 };
   struct Slot {
     og_request r;
     int S = 1, n_seg = 1;
     og::cpx<T>*cur_hi, *cur_lo, *lam_hi, *lam_lo, *za, *zb, *ck_hi, *ck_lo, *sg_hi, *sg_lo, *coefF, *coefA;
     double* part;
+    // resident states (packed Hermitian halves) of the slices jt .. n_t - 1
+    og::cpx<T>* tail = nullptr;
+    int n_tail = 0, jt = 0;
+    long ctxEH = 0;
+    og::cpx<T>* tl(int i) const { return tail + (long)i * ctxEH; }
     int phase = 0, j = 0, seg = 0, jj = 0, n = 0;
     bool inited = false;
     og::cpx<T>* ck(int i) const { return ck_hi + (long)i * ctxE; }
@@ -1631,13 +1636,18 @@ struct Engine : EngineBase {
   og_status serve_submit(const og_request& r, hipStream_t s) override {
     if (!banded) return fail(OG_ERR_SHAPE, "serving needs the banded path");
     if (ctx->ad_rtol > 0.0) return fail(OG_ERR_ARG, "serving runs fixed steps; disable adaptive steps");
-    if (ctx->resident > 0) return fail(OG_ERR_ARG, "serving keeps no resident states; og_set_resident(ctx, 0)");
+    if (ctx->resident > 0 && !(half_contract() && use_fused_slots(FWD) && use_fused_slots(ADJ)))
+      return fail(OG_ERR_ARG,
+                  "serving keeps resident states only as packed halves of fused steps; og_set_resident(ctx, 0)");
     if (r.ws_bytes < ws_bytes(1, r.n_t)) return fail(OG_ERR_WORKSPACE, "request workspace too small");
     Slot sl;
     sl.r = r;
     sl.ctxE = E;
-    sl.S = stride_for(r.n_t);
-    sl.n_seg = (r.n_t + sl.S - 1) / sl.S;
+    sl.ctxEH = EH;
+    sl.n_tail = tail_len(r.n_t);
+    sl.jt = r.n_t - sl.n_tail;
+    sl.S = stride_for(sl.jt);
+    sl.n_seg = (sl.jt + sl.S - 1) / sl.S;
     const Layout L = layout(1, r.n_t);
     char* p = static_cast<char*>(r.ws);
     auto at = [&](int i) { return reinterpret_cast<og::cpx<T>*>(p + L.off[i]); };
@@ -1654,6 +1664,7 @@ struct Engine : EngineBase {
     sl.coefF = at(L_COEF);
     sl.coefA = sl.coefF + (size_t)og::MAXA * d;
     sl.part = reinterpret_cast<double*>(p + L.off[L_GRAD]);
+    sl.tail = sl.n_tail > 0 ? at(L_TAIL) : nullptr;
     (void)s;
     slots.push_back(sl);
     return OG_OK;
@@ -1675,7 +1686,7 @@ struct Engine : EngineBase {
   }
   og_status start_segment(Slot& sl, hipStream_t s) {
     const int j0 = sl.seg * sl.S;
-    sl.n = std::min(sl.r.n_t, j0 + sl.S) - j0;
+    sl.n = std::min(sl.jt, j0 + sl.S) - j0;
     sl.jj = 0;
     sl.phase = PH_RECOMP;
     return copy1(sl.sg(0), sl.sgl(0), sl.ck(sl.seg), sl.ckl(sl.seg), s);
@@ -1687,6 +1698,8 @@ struct Engine : EngineBase {
     const og::cpx<T>*ihi, *ilo;
     og::cpx<T>*ohi, *olo;
     const og::cpx<T>* pairX;
+    og::cpx<T>* pk = nullptr;  // forward: the packed half of the result as well
+    bool xpacked = false;      // adjoint: pairX is a packed half
   };
 
   template <int MODE, int NA, int ND, bool LAD = false>
@@ -1724,6 +1737,7 @@ struct Engine : EngineBase {
           const Op& o = ops[i0 + q0 + q];
           const Slot& sl = slots[o.slot];
           ps.X[q] = o.pairX;
+          ps.xp[q] = o.xpacked ? 1 : 0;
           ps.L[q] = sl.lam_hi;
           ps.out[q] = sl.part + (long)o.slice * og::NCH * K;
         }
@@ -1780,6 +1794,7 @@ struct Engine : EngineBase {
             og::cpx<T>*& alt = dr == FWD ? sl.za : sl.zb;
             e.s_hi = cur;
             e.o_hi = alt;
+            e.pk = sub == nsub - 1 ? o.pk : nullptr;
             e.s_lo = e.o_lo = dr == FWD ? sl.cur_lo : sl.lam_lo;
             std::swap(cur, alt);
           } else {
@@ -1848,6 +1863,18 @@ struct Engine : EngineBase {
     return OG_OK;
   }
 
+  // the request's gradient from its partial sums; the request is done
+  og_status finish(Slot& sl, hipStream_t s) {
+    if (K > 0) {
+      const long nn = (long)sl.r.n_t * K;
+      og::reduce_partials_kernel<<<dim3((unsigned)((nn + 255) / 256)), 256, 0, s>>>(sl.part, sl.r.n_t, K,
+                                                                                    sl.r.grad);
+      OG_CHECK_LAUNCH();
+    }
+    sl.phase = PH_DONE;
+    return OG_OK;
+  }
+
   og_status serve_step(int max_slices, hipStream_t s, std::vector<long>& done) override {
     st = s;
     for (int it = 0; it < max_slices && !slots.empty(); ++it) {
@@ -1867,12 +1894,35 @@ struct Engine : EngineBase {
                                                   sl.r.phi);
               OG_CHECK_LAUNCH();
               OG_TRY(load1(sl.r.sigma, 0, sl.lam_hi, sl.lam_lo, s));
+              if (sl.n_tail > 0) {  // the resident slices first, then the recomputed segments
+                sl.phase = PH_TAIL;
+                sl.jj = sl.n_tail - 1;
+                continue;
+              }
               sl.seg = sl.n_seg - 1;
               OG_TRY(start_segment(sl, s));
               continue;
             }
-            if (sl.j % sl.S == 0) OG_TRY(copy1(sl.ck(sl.j / sl.S), sl.ckl(sl.j / sl.S), sl.cur_hi, sl.cur_lo, s));
-            fwd.push_back(Op{(int)i, sl.j, sl.cur_hi, sl.cur_lo, sl.cur_hi, sl.cur_lo, nullptr});
+            if (sl.j < sl.jt && sl.j % sl.S == 0)
+              OG_TRY(copy1(sl.ck(sl.j / sl.S), sl.ckl(sl.j / sl.S), sl.cur_hi, sl.cur_lo, s));
+            Op o{(int)i, sl.j, sl.cur_hi, sl.cur_lo, sl.cur_hi, sl.cur_lo, nullptr};
+            if (sl.j >= sl.jt) o.pk = sl.tl(sl.j - sl.jt + 1);
+            fwd.push_back(o);
+            break;
+          }
+          if (sl.phase == PH_TAIL) {
+            if (sl.jj < 0) {
+              if (sl.n_seg > 0) {
+                sl.seg = sl.n_seg - 1;
+                OG_TRY(start_segment(sl, s));
+                continue;
+              }
+              OG_TRY(finish(sl, s));
+              break;
+            }
+            Op o{(int)i, sl.jt + sl.jj, sl.lam_hi, sl.lam_lo, sl.lam_hi, sl.lam_lo, sl.tl(sl.jj + 1)};
+            o.xpacked = true;
+            adj.push_back(o);
             break;
           }
           if (sl.phase == PH_RECOMP) {
@@ -1891,13 +1941,7 @@ struct Engine : EngineBase {
                 OG_TRY(start_segment(sl, s));
                 continue;
               }
-              if (K > 0) {
-                const long nn = (long)sl.r.n_t * K;
-                og::reduce_partials_kernel<<<dim3((unsigned)((nn + 255) / 256)), 256, 0, s>>>(sl.part, sl.r.n_t, K,
-                                                                                              sl.r.grad);
-                OG_CHECK_LAUNCH();
-              }
-              sl.phase = PH_DONE;
+              OG_TRY(finish(sl, s));
               break;
             }
             adj.push_back(Op{(int)i, sl.seg * sl.S + sl.jj, sl.lam_hi, sl.lam_lo, sl.lam_hi, sl.lam_lo,

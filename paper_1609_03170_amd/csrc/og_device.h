@@ -1170,6 +1170,7 @@ struct FusedSlot {
   cpx<T>* o_hi;
   cpx<T>* o_lo;
   const double* urow;  // this request's controls u[j, :] of its slice
+  cpx<T>* pk;          // the packed Hermitian half of the output as well (nullptr: none)
 };
 template <typename T>
 struct FusedSlotTable {
@@ -1192,7 +1193,7 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 4 && NW == 4 ? 3 : 2) void rk
   P.ohi = s.o_hi;
   P.olo = s.o_lo;
   P.ex[0] = P.ex[1] = P.ex[2] = nullptr;
-  P.pk = nullptr;
+  P.pk = s.pk;
   rk4_fused_body<T, NQ, NW, S, true>(g, P, nullptr, drt, h, status, t, d, buf, fo, s.urow);
 }
 
@@ -1779,6 +1780,7 @@ struct PairSlots {
   const cpx<T>* X[MAXSLOT];
   const cpx<T>* L[MAXSLOT];
   double* out[MAXSLOT];
+  int xp[MAXSLOT];  // X is the packed Hermitian half (band_contract_half_slots_kernel)
 };
 
 template <typename T, int NH>
@@ -2026,7 +2028,7 @@ __global__ __launch_bounds__(256) void band_contract_half_slots_kernel(PairSlots
   double acc[FCK];
 #pragma unroll
   for (int k = 0; k < FCK; ++k) acc[k] = 0.0;
-  contract_half_chunk<T, NQ>(ps.X[b], 0, ps.L[b], cf, N, hw, k0, d, ch, acc, sm);
+  contract_half_chunk<T, NQ>(ps.X[b], ps.xp[b], ps.L[b], cf, N, hw, k0, d, ch, acc, sm);
   write_partials(sh, acc, K, ps.out[b], (long)ch * K, 0);
 }
 

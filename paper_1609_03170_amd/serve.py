@@ -48,13 +48,18 @@ class ServingLoop:
     byte budget."""
 
     def __init__(self, models: dict, *, prec="f32", budget_bytes=16 << 30, max_slices=8, max_active=4096,
-                 device=None):
+                 resident=False, device=None):
+        """resident: every request keeps the packed Hermitian halves of all
+        its forward states (no checkpoint recompute in its backward sweep;
+        more device bytes per request, counted against the budget)."""
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
         self.budget = int(budget_bytes)
         self.max_slices = int(max_slices)
         self.problems, self.servers, self.streams, self.sigma, self.rho0 = {}, {}, {}, {}, {}
         for key, w in models.items():
             p = Problem.from_workload(w, prec=prec, path="banded", gmode="grape1", device=self.device)
+            if resident:
+                p.set_resident(1 << 30)  # every slice of every request
             self.problems[key] = p
             self.servers[key] = Server(p, max_active=max_active)
             self.streams[key] = torch.cuda.Stream(device=self.device)

@@ -86,8 +86,9 @@ def test_resident_workspace_budget_and_serving_refusal():
     assert p.workspace_bytes(2, 50) <= budget
     with pytest.raises(OgError):
         p.set_resident(-1)
-    # serving keeps no resident states
+    # servers keep resident states only as the packed halves of fused steps
     p.set_resident(3)
+    p.set_fused(False)
     srv = Server(p)
     dev = torch.device("cuda", 0)
     u = torch.tensor(w.u[0][:4], device=dev)

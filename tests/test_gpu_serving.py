@@ -64,6 +64,28 @@ def test_mix_matches_alone_and_oracle():
     loop.close()
 
 
+@pytest.mark.parametrize("resident", [7, 1 << 30])
+def test_resident_serving_bitwise(resident):
+    """Requests that keep the packed halves of their last `resident` forward
+    states (a tail and recomputed segments before it, or every state) give
+    the bits of requests that keep none."""
+    reqs = _trace(10, seed=5, n_t_range=(20, 60))
+    base, _ = _loop()
+    ref = base.run(reqs, wl.serving_controls, keep=True)
+    base.close()
+    loop, _ = _loop()
+    for p in loop.problems.values():
+        p.set_resident(resident)
+    say(f"[case] serving {len(reqs)} requests with resident={resident}")
+    out = loop.run(reqs, wl.serving_controls, keep=True)
+    assert len(out.latencies) == len(reqs)
+    for r in reqs:
+        a = [t.cpu().numpy() for t in out.results[r["id"]]]
+        b = [t.cpu().numpy() for t in ref.results[r["id"]]]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), r
+    loop.close()
+
+
 def test_budget_admission_bounds_memory():
     reqs = _trace(8, seed=11)
     loop, models = _loop(budget=1)  # room for a single request at a time
