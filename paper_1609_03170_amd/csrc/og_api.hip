@@ -1728,9 +1728,11 @@ struct Engine : EngineBase {
   // operations first contract the first-order gradient of their slice.
   og_status run_chunk(int dr, const std::vector<Op>& ops, size_t i0, size_t i1, double dtv) {
     const int n = (int)(i1 - i0);
-    // contraction and coefficients: sub-launches of at most MAXSLOT requests
-    for (int q0 = 0; q0 < n; q0 += og::MAXSLOT) {
-      const int m = std::min(og::MAXSLOT, n - q0);
+    // contraction and coefficients: sub-launches of at most MAXPSLOT requests
+    // (MAXSLOT with the stage kernels' coefficient table)
+    const int per = use_fused_slots(dr) ? og::MAXPSLOT : og::MAXSLOT;
+    for (int q0 = 0; q0 < n; q0 += per) {
+      const int m = std::min(per, n - q0);
       if (dr == ADJ && K > 0) {
         og::PairSlots<T> ps{};
         for (int q = 0; q < m; ++q) {

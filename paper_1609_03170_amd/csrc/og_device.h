@@ -1775,12 +1775,13 @@ __global__ __launch_bounds__(256) void band_contract_kernel(PairArgs<T> pa, HBan
 
 // Slot-table variant (first-order gradient of one slice per slot): partials
 // of slot b go to out[b][chunk][k].
+constexpr int MAXPSLOT = 64;  // requests per contraction launch (the fused serving step's count)
 template <typename T>
 struct PairSlots {
-  const cpx<T>* X[MAXSLOT];
-  const cpx<T>* L[MAXSLOT];
-  double* out[MAXSLOT];
-  int xp[MAXSLOT];  // X is the packed Hermitian half (band_contract_half_slots_kernel)
+  const cpx<T>* X[MAXPSLOT];
+  const cpx<T>* L[MAXPSLOT];
+  double* out[MAXPSLOT];
+  int xp[MAXPSLOT];  // X is the packed Hermitian half (band_contract_half_slots_kernel)
 };
 
 template <typename T, int NH>
