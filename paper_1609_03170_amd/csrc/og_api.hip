@@ -372,12 +372,21 @@ struct Engine : EngineBase {
   og::FusedGeo fgeo[2]{};
   size_t fused_lds[2] = {0, 0};
   size_t fused_lds_slots[2] = {0, 0};  // serving launches: + the coefficient rows of the window
+  // the same step on smaller tiles (two more n-blocks per axis) for the
+  // smallest grids: more, shorter blocks
+  og::FusedGeo fgeo_s[2];
+  size_t fused_lds_s[2] = {0, 0};
+  size_t fused_lds_slots_s[2] = {0, 0};
   // waves per fused-step block: 8 in float64; in float32 4 (four blocks per
   // CU), or 8 for grids of fewer than kFusedSmall blocks, which fill less
-  // than one round of the chip and wait on each block's own latency
+  // than one round of the chip and wait on each block's own latency; grids
+  // of fewer than kFusedTiny blocks also take the smaller tiles of fgeo_s
+  // (measured at d = 240: 20.3 instead of 22.1 us at 21 blocks, 33.5
+  // instead of 27.0 at 336)
   // (measured at d = 240: 8 waves 22 / 27 / 40 us at 21 / 336 / 672 blocks
   // against 32 / 34 / 40 us with 4; 4 waves ahead from 1008 blocks on)
   static constexpr int kFusedSmall = 768;
+  static constexpr int kFusedTiny = 128;
   // fused-step coefficient data per direction: A0 and A_k on the five
   // diagonals (0, +1, -1, -N, +N) row by row (d x 5, K x d x 5), the row
   // (d x 3) and column (d x FDR) factors of the dissipator taps
@@ -582,6 +591,16 @@ struct Engine : EngineBase {
     g.t2 = t2;
     fused_lds[s] = bytes;
     fused_lds_slots[s] = bytes_lc;
+    {
+      const int nbs = std::max(nb, std::min(nb + 2, N / 2));
+      const int tmax = (N + nbs - 1) / nbs;
+      og::FusedGeo& gs = fgeo_s[s];
+      gs = g;
+      gs.nb = nbs;
+      gs.ntile = nbs * (nbs + 1) / 2;
+      fused_lds_s[s] = (size_t)og::fused_lds_elems(nq, ws, tmax) * sizeof(og::cpx<T>);
+      fused_lds_slots_s[s] = (size_t)og::fused_lds_elems(nq, ws, tmax, true) * sizeof(og::cpx<T>);
+    }
     fused[s] = true;
     return OG_OK;
   }
@@ -1047,12 +1066,16 @@ struct Engine : EngineBase {
     io.pk = pk;  // the packed Hermitian half of the output as well
     io.pk_s = EH;
     const og::cpx<T>* cf = fcoef[dr] + (size_t)(jslice - fc0[dr]) * B * og::FSLOT * d;
-    const dim3 grid((unsigned)(B * fgeo[dr].ntile));
+    const long blocks = (long)B * fgeo[dr].ntile;
+    const bool small = blocks < kFusedTiny;
+    const og::FusedGeo& geo = small ? fgeo_s[dr] : fgeo[dr];
+    const dim3 grid((unsigned)(B * geo.ntile));
+    const size_t lds = small ? fused_lds_s[dr] : fused_lds[dr];
     const long pidx = ctx->prof_begin(st);
-    fused_dispatch(dr, (long)grid.x, [&](auto nq, auto sg, auto nw) {
+    fused_dispatch(dr, blocks, [&](auto nq, auto sg, auto nw) {
       constexpr int NW = decltype(nw)::value;
       og::rk4_fused_kernel<T, decltype(nq)::value, NW, decltype(sg)::value>
-          <<<grid, NW * 64, fused_lds[dr], st>>>(fgeo[dr], io, d, cf, fdr[dr], h);
+          <<<grid, NW * 64, lds, st>>>(geo, io, d, cf, fdr[dr], h);
     });
     OG_CHECK_LAUNCH();
     ctx->prof_end(pidx, st);
@@ -1807,13 +1830,16 @@ struct Engine : EngineBase {
             prev[q] = e.o_hi;
           }
         }
-        const dim3 grid((unsigned)(n * fgeo[dr].ntile));
+        const long blocks = (long)n * fgeo[dr].ntile;
+        const bool small = blocks < kFusedTiny;
+        const og::FusedGeo& geo = small ? fgeo_s[dr] : fgeo[dr];
+        const dim3 grid((unsigned)(n * geo.ntile));
+        const size_t lds = small ? fused_lds_slots_s[dr] : fused_lds_slots[dr];
         const long pidx = ctx->prof_begin(st);
-        fused_dispatch(dr, (long)grid.x, [&](auto nq, auto sg, auto nw) {
+        fused_dispatch(dr, blocks, [&](auto nq, auto sg, auto nw) {
           constexpr int NW = decltype(nw)::value;
           og::rk4_fused_slots_kernel<T, decltype(nq)::value, NW, decltype(sg)::value>
-              <<<grid, NW * 64, fused_lds_slots[dr], st>>>(fgeo[dr], ft, fops(dr), fdr[dr], h, ctx->status_dev,
-                                                           d);
+              <<<grid, NW * 64, lds, st>>>(geo, ft, fops(dr), fdr[dr], h, ctx->status_dev, d);
         });
         OG_CHECK_LAUNCH();
         ctx->prof_end(pidx, st);
