@@ -1168,13 +1168,14 @@ struct Engine : EngineBase {
     hp.hw = fhw;
     hp.K = K;
     hp.k0 = half_k0;
-    const dim3 cg((unsigned)(og::NCH * B));
+    const int nblk = std::min(og::half_units<T>(d), og::NCH);  // blocks per problem: one unit each if they fit
+    const dim3 cg((unsigned)(nblk * B));
     const int N = fgeo[FWD].N;
     switch (fgeo[FWD].nq) {
-      case 1: og::band_contract_half_kernel<T, 1><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
-      case 2: og::band_contract_half_kernel<T, 2><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
-      case 3: og::band_contract_half_kernel<T, 3><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
-      case 4: og::band_contract_half_kernel<T, 4><<<cg, 256, 0, st>>>(hp, N, d, grad, n_t, jslice); break;
+      case 1: og::band_contract_half_kernel<T, 1><<<cg, 256, 0, st>>>(hp, N, d, nblk, grad, n_t, jslice); break;
+      case 2: og::band_contract_half_kernel<T, 2><<<cg, 256, 0, st>>>(hp, N, d, nblk, grad, n_t, jslice); break;
+      case 3: og::band_contract_half_kernel<T, 3><<<cg, 256, 0, st>>>(hp, N, d, nblk, grad, n_t, jslice); break;
+      case 4: og::band_contract_half_kernel<T, 4><<<cg, 256, 0, st>>>(hp, N, d, nblk, grad, n_t, jslice); break;
       default: return fail(OG_ERR_ARG, "internal: Hermitian-half contraction without its level count");
     }
     OG_CHECK_LAUNCH();
@@ -1769,11 +1770,13 @@ struct Engine : EngineBase {
         const dim3 cg((unsigned)(og::NCH * m));
         const int hN = fgeo[FWD].N;
         if (half_contract()) {  // the same arithmetic as the batch entry points
+          const int nb = std::min(og::half_units<T>(d), og::NCH);
+          const dim3 hg((unsigned)(nb * m));
           switch (fgeo[FWD].nq) {
-            case 1: og::band_contract_half_slots_kernel<T, 1><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
-            case 2: og::band_contract_half_slots_kernel<T, 2><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
-            case 3: og::band_contract_half_slots_kernel<T, 3><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
-            default: og::band_contract_half_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d); break;
+            case 1: og::band_contract_half_slots_kernel<T, 1><<<hg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d, nb); break;
+            case 2: og::band_contract_half_slots_kernel<T, 2><<<hg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d, nb); break;
+            case 3: og::band_contract_half_slots_kernel<T, 3><<<hg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d, nb); break;
+            default: og::band_contract_half_slots_kernel<T, 4><<<hg, 256, 0, st>>>(ps, dtv, fhw, half_k0, K, hN, d, nb); break;
           }
         } else if (hband.nH <= 4)
           og::band_contract_slots_kernel<T, 4><<<cg, 256, 0, st>>>(ps, dtv, hband, K, d);

@@ -1842,12 +1842,22 @@ constexpr int half_lds_elems() {
   return (win > red ? win : red) + HT_ROWS * FCK * 5;
 }
 
-// acc[k] += coef * (the 2-less Im part of chunk ch's share of Tr(H_k X L)).
+// Work units of the half of a d x d matrix (64 CG columns by HT_ROWS rows).
+template <typename T>
+__host__ __device__ __forceinline__ int half_units(int d) {
+  const int TC = 64 * half_cg<T>(), nct = (d + TC - 1) / TC;
+  int u = 0;
+  for (int c = 0; c < nct; ++c) u += ((d < (c + 1) * TC ? d : (c + 1) * TC) + HT_ROWS - 1) / HT_ROWS;
+  return u;
+}
+
+// acc[k] += coef * (the 2-less Im part of the share of Tr(H_k X L) of the
+// units ch, ch + nblk, ...).
 template <typename T, int NQ>
 __device__ __forceinline__ void contract_half_chunk(const cpx<T>* __restrict__ X, int x_packed,
                                                     const cpx<T>* __restrict__ L, double coef, int N,
                                                     const cpx<T>* __restrict__ hw, int k0, int d, int ch,
-                                                    double* acc, cpx<T>* __restrict__ sm) {
+                                                    int nblk, double* acc, cpx<T>* __restrict__ sm) {
   constexpr int CG = half_cg<T>(), TC = 64 * CG, WC = half_wc<T, NQ>();
   constexpr int WR = HT_ROWS + 2 * NQ, NWIN = WR * WC;
   constexpr int NK = NQ > 1 ? 5 : 3;
@@ -1860,7 +1870,7 @@ __device__ __forceinline__ void contract_half_chunk(const cpx<T>* __restrict__ X
   const int nct = (d + TC - 1) / TC;
   int ct = 0, cu0 = 0;  // column tile of unit u, its first unit
   auto nrt = [&](int c) { return (min(d, (c + 1) * TC) + HT_ROWS - 1) / HT_ROWS; };
-  for (int u = ch;; u += NCH) {
+  for (int u = ch;; u += nblk) {
     while (ct < nct && u >= cu0 + nrt(ct)) cu0 += nrt(ct++);
     if (ct >= nct) break;
     const int c0 = ct * TC, r0 = (u - cu0) * HT_ROWS;
@@ -1999,21 +2009,26 @@ __device__ __forceinline__ void contract_half_chunk(const cpx<T>* __restrict__ X
   }
 }
 
+// grid = nblk * B (nblk = min(half_units(d), NCH) blocks per problem, one
+// partial slot each; block 0 of a problem clears the slots nblk .. NCH - 1).
 template <typename T, int NQ>
-__global__ __launch_bounds__(256) void band_contract_half_kernel(HalfPair<T> hp, int N, int d,
+__global__ __launch_bounds__(256) void band_contract_half_kernel(HalfPair<T> hp, int N, int d, int nblk,
                                                                  double* __restrict__ part, long n_t, int jslice) {
   __shared__ double sh[4][MAXK];
   __shared__ cpx<T> sm[half_lds_elems<T, NQ>()];
   // the chunks of one problem share an XCD (and its L2): their taps reach
   // into each other's rows
   const int Lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = Lb / NCH, ch = Lb - b * NCH;
+  const int b = Lb / nblk, ch = Lb - b * nblk;
   double acc[FCK];
 #pragma unroll
   for (int k = 0; k < FCK; ++k) acc[k] = 0.0;
   contract_half_chunk<T, NQ>(hp.X + (long)b * hp.x_s, hp.x_packed, hp.L + (long)b * hp.l_s, hp.coef, N, hp.hw,
-                             hp.k0, d, ch, acc, sm);
-  write_partials(sh, acc, hp.K, part, (((long)b * n_t + jslice) * NCH + ch) * hp.K, 0);
+                             hp.k0, d, ch, nblk, acc, sm);
+  double* pb = part + ((long)b * n_t + jslice) * NCH * hp.K;
+  write_partials(sh, acc, hp.K, pb, (long)ch * hp.K, 0);
+  if (ch == 0)
+    for (int e = nblk * hp.K + threadIdx.x; e < NCH * hp.K; e += 256) pb[e] = 0.0;
 }
 
 // Slot-table variant (serving): full X and L of slot b, partials to
@@ -2021,16 +2036,18 @@ __global__ __launch_bounds__(256) void band_contract_half_kernel(HalfPair<T> hp,
 template <typename T, int NQ>
 __global__ __launch_bounds__(256) void band_contract_half_slots_kernel(PairSlots<T> ps, double cf,
                                                                        const cpx<T>* __restrict__ hw, int k0, int K,
-                                                                       int N, int d) {
+                                                                       int N, int d, int nblk) {
   __shared__ double sh[4][MAXK];
   __shared__ cpx<T> sm[half_lds_elems<T, NQ>()];
   const int Lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int b = Lb / NCH, ch = Lb - b * NCH;
+  const int b = Lb / nblk, ch = Lb - b * nblk;
   double acc[FCK];
 #pragma unroll
   for (int k = 0; k < FCK; ++k) acc[k] = 0.0;
-  contract_half_chunk<T, NQ>(ps.X[b], ps.xp[b], ps.L[b], cf, N, hw, k0, d, ch, acc, sm);
+  contract_half_chunk<T, NQ>(ps.X[b], ps.xp[b], ps.L[b], cf, N, hw, k0, d, ch, nblk, acc, sm);
   write_partials(sh, acc, K, ps.out[b], (long)ch * K, 0);
+  if (ch == 0)
+    for (int e = nblk * K + threadIdx.x; e < NCH * K; e += 256) ps.out[b][e] = 0.0;
 }
 
 // Dense contraction: W_p = X_p L_p already formed by the GEMM; with HT_k the
