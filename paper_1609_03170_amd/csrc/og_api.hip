@@ -921,7 +921,8 @@ struct Engine : EngineBase {
     ctx->prof_end(pidx, st);
     // sum_m (C_m Y) (gamma_m / 2 C_m^dag): one product per m into its own
     // buffer (J times the blocks of a single product with inner size J d),
-    // summed in the epilogue; beyond GM collapse operators one product
+    // each Hermitian and formed on and above the block diagonal only, summed
+    // in the epilogue; beyond GM collapse operators one full product
     // accumulates into X.
     int np = 0;
     if (J > 0 && J <= og::GM) {
@@ -940,7 +941,9 @@ struct Engine : EngineBase {
         h.sC[m] = (long)J * E;
         h.ldc[m] = d;
       }
-      const dim3 hg((d + 63) / 64, (d + 63) / 64, (unsigned)(B * J));
+      h.upper = 1;
+      const int nt = (d + 63) / 64;
+      const dim3 hg((unsigned)(nt * (nt + 1) / 2), 1, (unsigned)(B * J));
       launch_gemm(h, hg);
       OG_CHECK_LAUNCH();
       np = J;

@@ -87,17 +87,22 @@ __device__ __forceinline__ int xcd_logical_block(int id, int n) {
   return (n & 7) == 0 ? (id & 7) * (n >> 3) + (id >> 3) : id;
 }
 
-// (row, column) of the t-th upper-triangular 32 x 32 tile of a d x d matrix
-// in row-major order (tile row i holds the tiles i .. nt - 1), computed from
-// the index so that a block's first memory access is already its data.
-__device__ __forceinline__ int2 upper_tile(int t, int d) {
-  const int nt = (d + 31) / 32;
+// (row, column) of the t-th tile of the upper block triangle of an nt x nt
+// tile grid in row-major order (tile row i holds the tiles i .. nt - 1),
+// computed from the index so that a block's first memory access is already
+// its data.
+__device__ __forceinline__ int2 upper_of(int t, int nt) {
   int i = 0;
   while (t >= nt - i) {
     t -= nt - i;
     ++i;
   }
   return make_int2(i, i + t);
+}
+
+// the same for the 32 x 32 tiles of a d x d matrix
+__device__ __forceinline__ int2 upper_tile(int t, int d) {
+  return upper_of(t, (d + 31) / 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -1198,16 +1203,23 @@ __global__ __launch_bounds__(NW * 64, sizeof(T) == 4 && NW == 4 ? 3 : 2) void rk
 }
 
 // ---------------------------------------------------------------------------
-// Dense right-hand side epilogue: L(Y) = X + X^dag with X = A Y + 1/2 sum
-// gamma C Y C^dag already formed by the GEMMs; then the Runge-Kutta stage.
+// Dense right-hand side epilogue: L(Y) = X + X^dag + sum_m (P_m + P_m^dag)
+// with X = A Y and P_m = (C_m Y)(gamma_m / 2 C_m^dag) already formed by the
+// GEMMs; then the Runge-Kutta stage.  P_m is Hermitian, so P_m + P_m^dag =
+// 2 P_m, and only its tiles on and above the block diagonal are formed.
+// Beyond the products held apart (np = 0), X already holds the sum of the
+// P_m and L(Y) = X + X^dag.
 // ---------------------------------------------------------------------------
-// X of problem b is the sum of X[b] and the np partial products
-// Pp[b][m] (m < np, stride p_s per problem, d^2 per product), in that order.
+// Upper element e of X[b] + 2 sum_m Pp[b][m] (m < np, stride p_s per
+// problem, d^2 per product), summed in that order; the doubling is exact.
 template <typename T>
 __device__ __forceinline__ cpx<T> x_sum(const cpx<T>* __restrict__ Xb, const cpx<T>* __restrict__ Pb, int np,
                                         long e, long E) {
   cpx<T> v = Xb[e];
-  for (int m = 0; m < np; ++m) v = cadd(v, Pb[(long)m * E + e]);
+  for (int m = 0; m < np; ++m) {
+    const cpx<T> p = Pb[(long)m * E + e];
+    v = cadd(v, mkc<T>(p.re + p.re, p.im + p.im));
+  }
   return v;
 }
 
@@ -1232,7 +1244,7 @@ __global__ __launch_bounds__(256) void dense_stage_kernel(const cpx<T>* __restri
   for (int q = 0; q < 4; ++q) {
     const int r = ty + 8 * q;
     const int row = J0 + r, col = I0 + tx;
-    tT[r][tx] = (row < d && col < d) ? x_sum(Xb, Pb, np, (long)row * d + col, E) : mkc<T>(0, 0);
+    tT[r][tx] = (row < d && col < d) ? Xb[(long)row * d + col] : mkc<T>(0, 0);
   }
   __syncthreads();
   cpx<T> val[4];
@@ -1267,7 +1279,21 @@ struct GemmArgs {
   int nm;
   int M, N, Kd;
   cpx<T> alpha, beta;
+  // nonzero: only the 64 x 64 tiles on and above the block diagonal
+  // (M == N, a Hermitian product whose lower tiles are not read); the grid
+  // is then (nt (nt + 1) / 2, 1, batch) with nt = ceil(N / 64)
+  int upper;
 };
+
+// first row and column of a GEMM block's 64 x 64 output tile
+template <typename T>
+__device__ __forceinline__ int2 gemm_tile(const GemmArgs<T>& g) {
+  if (g.upper) {
+    const int2 t = upper_of(blockIdx.x, (g.N + 63) / 64);
+    return make_int2(t.x * 64, t.y * 64);
+  }
+  return make_int2(blockIdx.y * 64, blockIdx.x * 64);
+}
 
 template <typename T>
 struct Mfma;
@@ -1303,7 +1329,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
   cpx<T>* __restrict__ C = g.C[m] + (long)b * g.sC[m];
   const int lda = g.lda[m], ldb = g.ldb[m], ldc = g.ldc[m];
   const int M = g.M, N = g.N, Kd = g.Kd;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int2 t0 = gemm_tile(g);
+  const int m0 = t0.x, n0 = t0.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   // float64: four real products per complex product (cr = Re, ci = Im);
@@ -1478,7 +1505,8 @@ __global__ __launch_bounds__(256) void zgemm_split_kernel(GemmArgs<float> g) {
   cpx<float>* __restrict__ C = g.C[m] + (long)b * g.sC[m];
   const int lda = g.lda[m], ldb = g.ldb[m], ldc = g.ldc[m];
   const int M = g.M, N = g.N, Kd = g.Kd;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int2 t0 = gemm_tile(g);
+  const int m0 = t0.x, n0 = t0.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const float sc = S::scale;
