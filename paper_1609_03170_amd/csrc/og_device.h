@@ -1285,14 +1285,23 @@ struct GemmArgs {
   int upper;
 };
 
-// first row and column of a GEMM block's 64 x 64 output tile
+// First row, first column and batch entry of a GEMM block's 64 x 64 output
+// tile.  The blocks of one batch entry (which share its operands) are kept
+// on one XCD: the linear block index is mapped so that each XCD's blocks form
+// one contiguous range of (batch entry, tile), the tiles of an entry in
+// row-major order.
 template <typename T>
-__device__ __forceinline__ int2 gemm_tile(const GemmArgs<T>& g) {
+__device__ __forceinline__ int3 gemm_block(const GemmArgs<T>& g) {
+  const int per = gridDim.x * gridDim.y;
+  const int id = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int L = xcd_logical_block(id, per * gridDim.z);
+  const int z = L / per, t = L - z * per;
   if (g.upper) {
-    const int2 t = upper_of(blockIdx.x, (g.N + 63) / 64);
-    return make_int2(t.x * 64, t.y * 64);
+    const int2 u = upper_of(t, (g.N + 63) / 64);
+    return make_int3(u.x * 64, u.y * 64, z);
   }
-  return make_int2(blockIdx.y * 64, blockIdx.x * 64);
+  const int ty = t / gridDim.x;
+  return make_int3(ty * 64, (t - ty * gridDim.x) * 64, z);
 }
 
 template <typename T>
@@ -1322,15 +1331,15 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
   constexpr int BM = 64, BN = 64, BK = 16, PAD = 4;
   __shared__ T Ar[BK][BM + PAD], Ai[BK][BM + PAD];
   __shared__ T Br[BK][BN + PAD], Bi[BK][BN + PAD];
-  const int z = blockIdx.z;
+  const int3 blk = gemm_block(g);
+  const int z = blk.z;
   const int b = z / g.nm, m = z - b * g.nm;
   const cpx<T>* __restrict__ A = g.A[m] + (long)b * g.sA[m];
   const cpx<T>* __restrict__ Bm = g.B[m] + (long)b * g.sB[m];
   cpx<T>* __restrict__ C = g.C[m] + (long)b * g.sC[m];
   const int lda = g.lda[m], ldb = g.ldb[m], ldc = g.ldc[m];
   const int M = g.M, N = g.N, Kd = g.Kd;
-  const int2 t0 = gemm_tile(g);
-  const int m0 = t0.x, n0 = t0.y;
+  const int m0 = blk.x, n0 = blk.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   // float64: four real products per complex product (cr = Re, ci = Im);
@@ -1498,15 +1507,15 @@ __global__ __launch_bounds__(256) void zgemm_split_kernel(GemmArgs<float> g) {
   constexpr int BM = 64, BN = 64, BK = 32, KP = BK + 8;  // padded k extent
   __shared__ __attribute__((aligned(16))) e_t As[4][BM][KP];
   __shared__ __attribute__((aligned(16))) e_t Bs[4][BN][KP];
-  const int z = blockIdx.z;
+  const int3 blk = gemm_block(g);
+  const int z = blk.z;
   const int b = z / g.nm, m = z - b * g.nm;
   const cpx<float>* __restrict__ A = g.A[m] + (long)b * g.sA[m];
   const cpx<float>* __restrict__ Bm = g.B[m] + (long)b * g.sB[m];
   cpx<float>* __restrict__ C = g.C[m] + (long)b * g.sC[m];
   const int lda = g.lda[m], ldb = g.ldb[m], ldc = g.ldc[m];
   const int M = g.M, N = g.N, Kd = g.Kd;
-  const int2 t0 = gemm_tile(g);
-  const int m0 = t0.x, n0 = t0.y;
+  const int m0 = blk.x, n0 = blk.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const float sc = S::scale;
