@@ -1328,9 +1328,18 @@ struct Mfma<double> {
 template <typename T>
 __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
   typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int BM = 64, BN = 64, BK = 16, PAD = 4;
-  __shared__ T Ar[BK][BM + PAD], Ai[BK][BM + PAD];
-  __shared__ T Br[BK][BN + PAD], Bi[BK][BN + PAD];
+  // The tiles are unpadded with their columns permuted per k row (column c
+  // of row kk stored at c ^ sw(kk)), so that the A tile's stores (16 k rows
+  // of one or two adjacent columns per LDS cycle) and the MFMA operand reads
+  // (16 adjacent columns of one or two k rows) hit distinct banks.  float32
+  // (a cycle serves 32 lanes, one bank each): sw moves kk into bits 1-4,
+  // odd rows to the other 16 banks; float64 (16 lanes, two banks each):
+  // sw = kk.  With padded rows of 68 the float32 reads conflicted two-way
+  // and the float64 stores four-way.
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ T Ar[BK][BM], Ai[BK][BM];
+  __shared__ T Br[BK][BN], Bi[BK][BN];
+  auto sw = [](int kk) { return sizeof(T) == 4 ? (((kk >> 1) << 1) | ((kk & 1) << 4)) : kk; };
   const int3 blk = gemm_block(g);
   const int z = blk.z;
   const int b = z / g.nm, m = z - b * g.nm;
@@ -1380,28 +1389,28 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int r = e >> 4, kk = e & 15;
-      Ar[kk][r] = va[q].re;
-      Ai[kk][r] = va[q].im;
+      Ar[kk][r ^ sw(kk)] = va[q].re;
+      Ai[kk][r ^ sw(kk)] = va[q].im;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int kk = e >> 6, c = e & 63;
-      Br[kk][c] = vb[q].re;
-      Bi[kk][c] = vb[q].im;
+      Br[kk][c ^ sw(kk)] = vb[q].re;
+      Bi[kk][c ^ sw(kk)] = vb[q].im;
     }
     __syncthreads();
     if (k0 + BK < Kd) load_step(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
+      const int kk = ks * 4 + (lane >> 4), x = sw(kk);
       T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        ar[a] = Ar[kk][wm + a * 16 + (lane & 15)];
-        ai[a] = Ai[kk][wm + a * 16 + (lane & 15)];
-        br[a] = Br[kk][wn + a * 16 + (lane & 15)];
-        bi[a] = Bi[kk][wn + a * 16 + (lane & 15)];
+        ar[a] = Ar[kk][(wm + a * 16 + (lane & 15)) ^ x];
+        ai[a] = Ai[kk][(wm + a * 16 + (lane & 15)) ^ x];
+        br[a] = Br[kk][(wn + a * 16 + (lane & 15)) ^ x];
+        bi[a] = Bi[kk][(wn + a * 16 + (lane & 15)) ^ x];
       }
       if constexpr (G3) {
         T as[2], bs[2];
