@@ -1325,8 +1325,12 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
-template <typename T>
-__global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
+// NB = 2: two LDS buffers per operand tile, one barrier per K step (the next
+// step's tiles are stored while the matrix cores work on the current one);
+// used for grids that fill the chip several blocks per CU deep, where the
+// co-resident blocks otherwise reach their barriers together.
+template <typename T, int NB = 1>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : (NB == 2 ? 4 : 1)) void zgemm_kernel(GemmArgs<T> g) {
   typedef typename Mfma<T>::acc_t acc_t;
   // The tiles are unpadded with their columns permuted per k row (column c
   // of row kk stored at c ^ sw(kk)), so that the A tile's stores (16 k rows
@@ -1337,8 +1341,8 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
   // sw = kk.  With padded rows of 68 the float32 reads conflicted two-way
   // and the float64 stores four-way.
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ T Ar[BK][BM], Ai[BK][BM];
-  __shared__ T Br[BK][BN], Bi[BK][BN];
+  __shared__ T Ar[NB][BK][BM], Ai[NB][BK][BM];
+  __shared__ T Br[NB][BK][BN], Bi[NB][BK][BN];
   auto sw = [](int kk) { return sizeof(T) == 4 ? (((kk >> 1) << 1) | ((kk & 1) << 4)) : kk; };
   const int3 blk = gemm_block(g);
   const int z = blk.z;
@@ -1383,34 +1387,33 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
       vb[q] = (gk < Kd && gn < N) ? Bm[(long)gk * ldb + gn] : mkc<T>(0, 0);
     }
   };
-  load_step(0);
-  for (int k0 = 0; k0 < Kd; k0 += BK) {
+  auto store_step = [&](int sb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int r = e >> 4, kk = e & 15;
-      Ar[kk][r ^ sw(kk)] = va[q].re;
-      Ai[kk][r ^ sw(kk)] = va[q].im;
+      Ar[sb][kk][r ^ sw(kk)] = va[q].re;
+      Ai[sb][kk][r ^ sw(kk)] = va[q].im;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int kk = e >> 6, c = e & 63;
-      Br[kk][c ^ sw(kk)] = vb[q].re;
-      Bi[kk][c ^ sw(kk)] = vb[q].im;
+      Br[sb][kk][c ^ sw(kk)] = vb[q].re;
+      Bi[sb][kk][c ^ sw(kk)] = vb[q].im;
     }
-    __syncthreads();
-    if (k0 + BK < Kd) load_step(k0 + BK);
+  };
+  auto compute_step = [&](int sb) {
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4), x = sw(kk);
       T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        ar[a] = Ar[kk][(wm + a * 16 + (lane & 15)) ^ x];
-        ai[a] = Ai[kk][(wm + a * 16 + (lane & 15)) ^ x];
-        br[a] = Br[kk][(wn + a * 16 + (lane & 15)) ^ x];
-        bi[a] = Bi[kk][(wn + a * 16 + (lane & 15)) ^ x];
+        ar[a] = Ar[sb][kk][(wm + a * 16 + (lane & 15)) ^ x];
+        ai[a] = Ai[sb][kk][(wm + a * 16 + (lane & 15)) ^ x];
+        br[a] = Br[sb][kk][(wn + a * 16 + (lane & 15)) ^ x];
+        bi[a] = Bi[sb][kk][(wn + a * 16 + (lane & 15)) ^ x];
       }
       if constexpr (G3) {
         T as[2], bs[2];
@@ -1439,7 +1442,30 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmArgs<T> g) {
           }
       }
     }
+  };
+  load_step(0);
+  if constexpr (NB == 1) {
+    for (int k0 = 0; k0 < Kd; k0 += BK) {
+      store_step(0);
+      __syncthreads();
+      if (k0 + BK < Kd) load_step(k0 + BK);
+      compute_step(0);
+      __syncthreads();
+    }
+  } else {
+    // buffer cur is read in this step while buffer cur ^ 1, last read in the
+    // previous step (before its closing barrier), takes the next step's tiles
+    store_step(0);
     __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < Kd; k0 += BK) {
+      const bool next = k0 + BK < Kd;
+      if (next) load_step(k0 + BK);
+      compute_step(cur);
+      if (next) store_step(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
   }
   const cpx<T> al = g.alpha, be = g.beta;
   const bool use_beta = (be.re != T(0) || be.im != T(0));
